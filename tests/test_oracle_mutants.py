@@ -1,0 +1,92 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a private copy of the oracle's C source
+(on the CPU only: a dropped term, a wrong sign or index, a transposed
+output, a lost summand), builds it, and checks that at least one pin of
+``test_oracle_pins`` style rejects it.  The real oracle is untouched.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+from test_oracle_pins import exact_r_via_gram, lapack_r
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "drop_alpha_in_norm": ("sqrt(alpha * alpha + s)", "sqrt(s)"),
+    "drop_pivot_term_in_w": ("double w = ac[j] + pdot(", "double w = pdot("),
+    "shifted_index_in_w": ("pdot(a + j + 1, 1, ac + j + 1, 1, below)", "pdot(a + j + 1, 1, ac + j, 1, below)"),
+    "tau_over_alpha": ("double tau = (beta - alpha) / beta;", "double tau = (beta - alpha) / alpha;"),
+    "transposed_output": ("(c >= i) ? A[c * M + i] : 0.0", "(c >= i) ? A[i * M + c] : 0.0"),
+    "update_sign": ("ac[i] = ac[i] - tw * a[i]", "ac[i] = ac[i] + tw * a[i]"),
+    "pairwise_drops_last": ("b + h * sb, sb, len - h)", "b + h * sb, sb, len - h - 1)"),
+    "no_sign_normalisation": ("if (R[i * n + i] < 0.0)", "if (0)"),
+    "skip_pivot_update": ("ac[j] = ac[j] - tw;", ";"),
+    "scale_not_applied": ("a[i] = a[i] * scale;", "a[i] = a[i];"),
+}
+
+
+def build_mutant(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, name
+    src = src.replace(old, new, 1)
+    c = tmp_path / ("%s.c" % name)
+    so = tmp_path / ("%s.so" % name)
+    c.write_text(src)
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-w", str(c), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_householder_r.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp]
+    lib.oracle_householder_r.restype = ctypes.c_int
+    return lib
+
+
+def mutant_r(lib, X):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    R = np.empty((n, n))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_householder_r(X.ctypes.data_as(dp), m, n, n, R.ctypes.data_as(dp))
+    return R
+
+
+def pins_pass(r_of) -> bool:
+    """A compact battery of the independent pins."""
+    # exact rational R (tiny)
+    X = wl.dyadic(9, 3, seed=5)
+    Rx = exact_r_via_gram(X)
+    Rf = np.array([[float(v) for v in row] for row in Rx])
+    if not np.all(np.isfinite(r_of(X))) or oracle.rel_err_r(r_of(X), Rf) > 1e-13:
+        return False
+    # closed form n = 1
+    x = wl.gaussian(1000, 1, seed=3)
+    if abs(r_of(x)[0, 0] - np.sqrt(np.sum(x * x))) > 1e-13 * np.sqrt(np.sum(x * x)):
+        return False
+    # known R0 and LAPACK
+    Xk, R0 = wl.known_r(777, 6, wl.logspace_sigma(6, 3), seed=1)
+    Rk = r_of(Xk)
+    if not np.all(np.isfinite(Rk)) or oracle.rel_err_r(Rk, R0) > 1e-12:
+        return False
+    Xg = wl.gaussian(300, 5, seed=2)
+    if oracle.rel_err_r(r_of(Xg), lapack_r(Xg)) > 1e-13:
+        return False
+    return True
+
+
+def test_battery_accepts_real_oracle():
+    assert pins_pass(oracle.householder_r)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_battery_rejects_mutant(tmp_path, name):
+    lib = build_mutant(tmp_path, name)
+    with np.errstate(all="ignore"):
+        assert not pins_pass(lambda X: mutant_r(lib, X)), name
