@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark: Q-less TSQR HBM throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+
+A step is one complete ``qless_tsqr_r`` call (stage-1 streaming kernel, the
+stacked-R tree and the sign normalisation) on the 5e7 x 8 FP64 workload
+X = Q0 R0 with kappa = 1e4, resident in HBM.  ``value`` is algorithmic GB/s =
+8 m n bytes per step / step time.  The JSON line adds
+  roofline     : the stage-1 kernel's algorithmic bytes per launch over its
+                 average launch duration (HIP events around each launch on
+                 the launch stream), against the 8 TB/s HBM peak;
+  cpu_baseline : the CPU oracle (plain Householder, one thread) timed on this
+                 host on the same matrix;
+  sweep        : m = 2^25, n in {1, 2, 4, 8, 16, 32, 64} (kappa = 1e4):
+                 GB/s, fraction of HBM peak and FP64 TF/s per n;
+  compare      : CholQR2 and SVQB2 on the same 5e7 x 8 matrix when built.
+Only one GPU is used; --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+FP64_PEAK_TFS = 78.6        # MI355X FP64 vector, published
+
+
+def tsqr_bytes(m: int, n: int) -> int:
+    """Algorithmic bytes of Q-less TSQR: X read once (Sec. 3.2 model)."""
+    return 8 * m * n
+
+
+def tsqr_flops(m: int, n: int) -> int:
+    """Lower bound of the FP64 flop count: 2 m n^2 (Sec. 3.2 model)."""
+    return 2 * m * n * n
+
+
+def gram2_bytes(m: int, n: int) -> int:
+    """CholQR2 / SVQB2: two passes over X (Sec. 3.1 model)."""
+    return 16 * m * n
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_20889_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per stage-1 launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "tsqr_stage1_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("workload") != workload:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def time_calls(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / steps, wall
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--m", type=int, default=50_000_000)
+    ap.add_argument("--n", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rows would shard across GPUs with one n x n all-gather; see DESIGN.md).",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2603_20889_amd as q
+    import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    q.load()
+    m, n = args.m, args.n
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+
+    log("generating X = Q0 R0 (%d x %d, kappa 1e4) on the GPU" % (m, n))
+    X, R0 = wl.config2(m=m, n=n, device=dev)
+    torch.cuda.synchronize()
+    R = torch.empty((n, n), dtype=torch.float64, device=dev)
+    work, wb = q._workspace(q.QLESS_METHOD_TSQR, m, n, dev)
+
+    def step():
+        q.qless_tsqr_r(X, R=R, work=work)
+
+    log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    q.timing_reset()
+    q.timing_enable(True)
+    ms, wall = time_calls(step, args.steps, 0)
+    q.timing_enable(False)
+    st_ms, st_cnt = q.timing_read("tsqr_stage1")
+    q.timing_reset()
+    e_r = float(np.linalg.norm(R.cpu().numpy() - R0) / np.linalg.norm(R0))
+    log("step %.4f ms, stage-1 %.4f ms x %d, e_R vs R0 %.2e" % (ms, st_ms / max(st_cnt, 1), st_cnt, e_r))
+
+    nbytes = tsqr_bytes(m, n)
+    value = nbytes / (ms * 1e-3) / 1e9
+    st_avg = st_ms / max(st_cnt, 1)
+    achieved = nbytes / (st_avg * 1e-3) / 1e9
+    workload = "tsqr_config2_%dx%d" % (m, n)
+    traffic = load_traffic(workload)
+
+    out = {
+        "metric": "Q-less TSQR HBM GB/s (% of peak), n=1..64; batched solves/s + p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "qless_tsqr_r on X = Q0*R0, m=%d, n=%d, kappa=1e4, FP64 row-major, "
+                               "resident in HBM" % (m, n), "m": m, "n": n},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "tsqr_stage1", "kernel_ms": round(st_avg, 5),
+                     "algorithmic_bytes_per_launch": nbytes},
+        "accuracy": {"e_R_vs_R0": e_r},
+        "pct_hbm_peak_step": round(100.0 * value / HBM_PEAK_GBS, 2),
+    }
+
+    if not args.no_cpu:
+        import oracle
+        log("CPU oracle on the same matrix (host copy)")
+        Xh = X.cpu().numpy()
+        t0 = time.perf_counter()
+        Ro = oracle.householder_r(Xh)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+                               "kind": "oracle", "seconds": round(dt, 3),
+                               "sample": "the full %d x %d benchmark matrix, one call of the "
+                                         "single-threaded oracle" % (m, n)}
+        out["accuracy"]["e_R_vs_oracle"] = float(np.linalg.norm(R.cpu().numpy() - Ro) / np.linalg.norm(Ro))
+        del Xh
+
+    del X, work
+    torch.cuda.empty_cache()
+
+    if not args.no_sweep:
+        sweep = []
+        ms_s = 2 ** 25
+        for ns in (1, 2, 4, 8, 16, 32, 64):
+            log("sweep m=2^25 n=%d" % ns)
+            Xs, R0s = wl.config3(ns, 4, device=dev)
+            Rs = torch.empty((ns, ns), dtype=torch.float64, device=dev)
+            ws, _ = q._workspace(q.QLESS_METHOD_TSQR, ms_s, ns, dev)
+            steps = 20 if ns <= 16 else 5
+            flush = torch.empty(2 ** 27, dtype=torch.float64, device=dev) if ns <= 4 else None
+
+            def f():
+                if flush is not None:      # evict the MALL between calls: 1 GiB write
+                    flush.zero_()
+                q.qless_tsqr_r(Xs, R=Rs, work=ws)
+
+            q.timing_reset()
+            q.timing_enable(True)
+            t_ms, _ = time_calls(f, steps, 2)
+            q.timing_enable(False)
+            k_ms, k_cnt = q.timing_read("tsqr_stage1")
+            q.timing_reset()
+            k_avg = k_ms / max(k_cnt, 1)
+            if flush is not None:
+                t_ms = None  # the step time includes the flush; report the kernel time only
+            er = float(np.linalg.norm(Rs.cpu().numpy() - R0s) / np.linalg.norm(R0s))
+            rec = {"n": ns, "stage1_ms": round(k_avg, 5),
+                   "stage1_GBps": round(tsqr_bytes(ms_s, ns) / (k_avg * 1e-3) / 1e9, 1),
+                   "stage1_frac_hbm": round(tsqr_bytes(ms_s, ns) / (k_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "stage1_TFps": round(tsqr_flops(ms_s, ns) / (k_avg * 1e-3) / 1e12, 2),
+                   "e_R": er}
+            if t_ms is not None:
+                rec["step_ms"] = round(t_ms, 5)
+                rec["step_GBps"] = round(tsqr_bytes(ms_s, ns) / (t_ms * 1e-3) / 1e9, 1)
+            sweep.append(rec)
+            log(json.dumps(rec))
+            del Xs, ws, flush
+            torch.cuda.empty_cache()
+        out["sweep"] = sweep
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,154 @@
+/*
+ * qless.h -- Q-less QR of tall, very skinny FP64 matrices on AMD MI355X (gfx950).
+ *
+ * Method: J. Thies, M. Roehrig-Zoellner, "Implementation of QR factorization
+ * of tall and very skinny matrices on current GPUs", arXiv 2603.20889.
+ *
+ * Problem (Sec. 1): for a real dense X (m x n, m >> n) find R (n x n, upper
+ * triangular) with X = QR and Q^T Q = I, returning only R ("Q-less": neither
+ * Q nor the Householder reflectors are ever written).
+ *
+ * Conventions shared by every entry point
+ *   - FP64 only.  X is ROW-MAJOR with leading dimension ldx >= n (element
+ *     (i, j) at X[i * ldx + j]); 64-bit indexing throughout.
+ *   - R (and Z) are n x n ROW-MAJOR with leading dimension ldr >= n.  Every
+ *     entry is written: zeros below the diagonal, diag(R) >= 0 (R is unique
+ *     only up to row signs; the sign of each row is fixed so its diagonal
+ *     entry is non-negative, and -0.0 is written as +0.0).
+ *   - m may be smaller than n (including m = 0): the result is then the R of
+ *     X padded with zero rows to n rows.  1 <= n <= QLESS_MAX_N.
+ *   - X, R, Z, sigma, info and work are DEVICE pointers owned by the caller.
+ *     The library never allocates, frees or synchronises in these calls;
+ *     every call only enqueues kernels on `stream` and returns.
+ *   - work/work_bytes: caller-provided device scratch of at least
+ *     qless_workspace_bytes(method, m, n) bytes, 256-byte aligned.  Two calls
+ *     that are in flight at the same time must not share a workspace.
+ *   - Errors found on the host (bad arguments, too-small workspace, launch
+ *     failure) are returned synchronously as a negative qless_status before
+ *     (or instead of) any launch.  Numerical conditions found on the device
+ *     are reported through `info` (see each function).
+ *   - Non-finite input propagates into the result; it is not checked.
+ *   - Results are deterministic: the same inputs, sizes and device give
+ *     bitwise-identical outputs (no atomics in any reduction).
+ */
+#ifndef QLESS_H
+#define QLESS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QLESS_MAX_N 64
+
+typedef enum {
+    QLESS_OK = 0,
+    QLESS_ERR_ARG = -1,          /* null pointer, n < 1, m < 0, ldx < n, ldr < n, ... */
+    QLESS_ERR_UNSUPPORTED = -2,  /* n > QLESS_MAX_N */
+    QLESS_ERR_WORKSPACE = -3,    /* work is NULL, misaligned or smaller than required */
+    QLESS_ERR_HIP = -4           /* a HIP runtime call or kernel launch failed */
+} qless_status;
+
+typedef enum {
+    QLESS_METHOD_TSQR = 0,       /* qless_tsqr_r */
+    QLESS_METHOD_CHOLQR2 = 1,    /* cholqr2_r */
+    QLESS_METHOD_SVQB = 2        /* svqb */
+} qless_method;
+
+typedef enum {
+    QLESS_SVQB_R = 0,            /* write R = qr_R(Z) (sign-normalised) */
+    QLESS_SVQB_QZ = 1            /* write Z of X = QZ */
+} qless_svqb_out;
+
+/* Human-readable name of a qless_status value. */
+const char *qless_status_string(int status);
+
+/* Library version string, e.g. "qless 0.1 gfx950". */
+const char *qless_version(void);
+
+/* Workspace size in bytes that `method` needs for an m x n problem on the
+ * current device (the size depends on the device's compute-unit count).
+ * Returns 0 for invalid arguments. */
+size_t qless_workspace_bytes(int method, int64_t m, int64_t n);
+
+/*
+ * qless_tsqr_r -- Q-less Householder TSQR (Alg. 2 with the per-block
+ * streaming kernel of Alg. 3 and the trapezoidal Householder step of Alg. 4).
+ *
+ * Stage 1: k row blocks, each factored by one wavefront that streams
+ * coalesced row panels and keeps its running R_i on chip; stage 2: a tree of
+ * stacked-R reductions R = R([R_1; ...; R_k]).  X is read exactly once; only
+ * the k small R_i (in `work`) and the final R are written.
+ *
+ * Arguments: X (m x n, ldx), R (n x n, ldr) as above.  X and R must not
+ * overlap.  Returns QLESS_OK or a negative qless_status.  Rank-deficient X
+ * is not an error: R then has (near-)zero diagonal entries (Sec. 1).
+ */
+int qless_tsqr_r(const double *X, int64_t m, int64_t n, int64_t ldx,
+                 double *R, int64_t ldr, void *work, size_t work_bytes,
+                 hipStream_t stream);
+
+/*
+ * cholqr2_r -- Q-less Cholesky-QR2 (Alg. 1): C = X^T X; R1 = chol(C);
+ * C = (X R1^{-1})^T (X R1^{-1}); R2 = chol(C); R = R2 R1.  Two passes over X;
+ * the n x n steps run on the device.  Suitable only for kappa(X) below about
+ * eps^{-1/2} (Sec. 3.1).
+ *
+ * info (device int32, may be NULL): 0 on success; j (1..n) if the first
+ * Cholesky meets a non-positive pivot in column j, n + j for the second
+ * Cholesky.  On breakdown every entry of R is NaN.
+ */
+int cholqr2_r(const double *X, int64_t m, int64_t n, int64_t ldx,
+              double *R, int64_t ldr, int32_t *info, void *work,
+              size_t work_bytes, hipStream_t stream);
+
+/*
+ * svqb -- Q-less SVQB applied twice (Sec. 1 and Sec. 3.1, SVQB2):
+ * C1 = X^T X = U1 L1 U1^T, D1 = U1 L1^{-1/2}; C2 = (X D1)^T (X D1) =
+ * U2 L2 U2^T; X = Q Z with Q = X D1 D2 (never formed) and
+ * Z = L2^{1/2} U2^T L1^{1/2} U1^T.  Entries of L^{-1/2} whose eigenvalue is
+ * <= trunc_tol * lambda_max are replaced by 0 (truncation); trunc_tol <= 0
+ * selects n * 2^-52.
+ *
+ * out = QLESS_SVQB_QZ writes Z (n x n, ldz); QLESS_SVQB_R writes
+ * R = qr_R(Z) with diag >= 0 (then R equals the R of X up to rounding).
+ * sigma (device, n doubles, may be NULL): square roots of the first-pass
+ * eigenvalues, decreasing.  info (device int32, may be NULL): number of
+ * truncated eigenvalues over both passes (informational, not an error).
+ */
+int svqb(const double *X, int64_t m, int64_t n, int64_t ldx, int out,
+         double *Z_or_R, int64_t ldz, double *sigma, double trunc_tol,
+         int32_t *info, void *work, size_t work_bytes, hipStream_t stream);
+
+/*
+ * qless_lstsq_finish -- least squares from the Q-less R of [A b] (Sec. 1):
+ * Rt = R([A b]) = [[RA, z], [0, rho]] ((n+1) x (n+1) row-major, ldr >= n+1)
+ * gives x = RA^{-1} z by back substitution and |rho| = ||A x - b||_2.
+ * x: device, n doubles.  resid: device, 1 double (may be NULL).
+ * info (device int32, may be NULL): 0, or j (1..n) if RA_jj == 0.
+ */
+int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
+                       double *resid, int32_t *info, hipStream_t stream);
+
+/* ---------------------------------------------------------- timing hooks */
+
+/*
+ * Optional per-kernel event timing for benchmarks.  While enabled, the
+ * library records a hipEvent pair around every launch of its stage-1 TSQR
+ * kernel ("tsqr_stage1") and Gram kernels ("gram") on the launch stream.
+ * qless_timing_read synchronises those events and returns the summed
+ * duration in milliseconds and the launch count since the last reset.
+ * Not thread-safe; intended for single-threaded benchmark drivers.
+ */
+int qless_timing_enable(int on);
+int qless_timing_reset(void);
+int qless_timing_read(const char *kernel, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QLESS_H */

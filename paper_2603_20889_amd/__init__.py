@@ -1,0 +1,236 @@
+"""qless: Q-less QR of tall, very skinny FP64 matrices on AMD MI355X (gfx950).
+
+Thin ctypes binding over the C-ABI library ``libqless.so`` (declared in
+``include/qless.h``).  Functions carry the C names; they only marshal
+arguments: PyTorch provides device memory (tensors) and the current stream,
+and every step of the computation runs in the library's HIP kernels.  There
+is no CPU fallback -- when the library is missing, ``load()`` raises.
+
+Method: Thies & Roehrig-Zoellner, "Implementation of QR factorization of tall
+and very skinny matrices on current GPUs", arXiv 2603.20889.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqless.so")
+
+QLESS_OK = 0
+QLESS_ERR_ARG = -1
+QLESS_ERR_UNSUPPORTED = -2
+QLESS_ERR_WORKSPACE = -3
+QLESS_ERR_HIP = -4
+
+QLESS_METHOD_TSQR = 0
+QLESS_METHOD_CHOLQR2 = 1
+QLESS_METHOD_SVQB = 2
+
+QLESS_SVQB_R = 0
+QLESS_SVQB_QZ = 1
+
+QLESS_MAX_N = 64
+
+EXPORTED = (
+    "qless_status_string", "qless_version", "qless_workspace_bytes", "qless_tsqr_r",
+    "cholqr2_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
+    "qless_timing_read",
+)
+
+
+class QlessError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s" % (where, status_string(status)))
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libqless.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libqless.so not found at %s; build it with "
+                           "`python -m paper_2603_20889_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sz = ctypes.c_size_t
+    lib.qless_status_string.argtypes = [ctypes.c_int]
+    lib.qless_status_string.restype = ctypes.c_char_p
+    lib.qless_version.argtypes = []
+    lib.qless_version.restype = ctypes.c_char_p
+    lib.qless_workspace_bytes.argtypes = [ctypes.c_int, i64, i64]
+    lib.qless_workspace_bytes.restype = sz
+    lib.qless_tsqr_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, sz, vp]
+    lib.qless_tsqr_r.restype = ctypes.c_int
+    lib.cholqr2_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
+    lib.cholqr2_r.restype = ctypes.c_int
+    lib.svqb.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, i64, vp, dbl, vp, vp, sz, vp]
+    lib.svqb.restype = ctypes.c_int
+    lib.qless_lstsq_finish.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+    lib.qless_lstsq_finish.restype = ctypes.c_int
+    lib.qless_timing_enable.argtypes = [ctypes.c_int]
+    lib.qless_timing_enable.restype = ctypes.c_int
+    lib.qless_timing_reset.argtypes = []
+    lib.qless_timing_reset.restype = ctypes.c_int
+    lib.qless_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.qless_timing_read.restype = ctypes.c_int
+    _ = i32
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().qless_status_string(int(status)).decode()
+    except RuntimeError:
+        return "status %d" % status
+
+
+def version() -> str:
+    return load().qless_version().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != QLESS_OK:
+        raise QlessError(status, where)
+
+
+# ------------------------------------------------------------ marshalling
+
+def _matrix(X, name="X"):
+    import torch
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.float64 or X.dim() != 2:
+        raise TypeError("%s must be a 2-D torch.float64 tensor" % name)
+    if X.device.type != "cuda":
+        raise TypeError("%s must live on a GPU (got %s)" % (name, X.device))
+    m, n = X.shape
+    if m > 0 and X.stride(1) != 1:
+        X = X.contiguous()
+    ldx = X.stride(0) if m > 1 else n
+    return X, int(m), int(n), int(max(ldx, n))
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(method: int, m: int, n: int, device):
+    import torch
+    nbytes = int(load().qless_workspace_bytes(method, m, n))
+    if nbytes == 0:
+        return None, 0
+    # torch's caching allocator returns 512-byte-aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def qless_workspace_bytes(method: int, m: int, n: int) -> int:
+    return int(load().qless_workspace_bytes(int(method), int(m), int(n)))
+
+
+def qless_tsqr_r(X, R=None, work=None):
+    """R (n x n, diag >= 0) of the GPU float64 matrix X by Q-less TSQR."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_TSQR, m, n, dev)
+        else:
+            wb = work.numel() * work.element_size()
+        st = load().qless_tsqr_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                                 ctypes.c_void_p(R.data_ptr()), R.stride(0),
+                                 ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb,
+                                 _stream(dev))
+    _check(st, "qless_tsqr_r")
+    return R
+
+
+def cholqr2_r(X, R=None, info=None, work=None):
+    """Q-less CholQR2 (Alg. 1).  Returns (R, info) with info a 1-element int32
+    device tensor (0 ok; j or n+j on Cholesky breakdown)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_CHOLQR2, m, n, dev)
+        else:
+            wb = work.numel() * work.element_size()
+        st = load().cholqr2_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                              ctypes.c_void_p(R.data_ptr()), R.stride(0), ctypes.c_void_p(info.data_ptr()),
+                              ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
+    _check(st, "cholqr2_r")
+    return R, info
+
+
+def svqb(X, out: int = QLESS_SVQB_R, trunc_tol: float = 0.0, Z=None, sigma=None, info=None, work=None):
+    """Q-less SVQB2.  Returns (Z_or_R, sigma, info)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if Z is None:
+            Z = torch.empty((n, n), dtype=torch.float64, device=dev)
+        if sigma is None:
+            sigma = torch.empty(n, dtype=torch.float64, device=dev)
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_SVQB, m, n, dev)
+        else:
+            wb = work.numel() * work.element_size()
+        st = load().svqb(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx, int(out),
+                         ctypes.c_void_p(Z.data_ptr()), Z.stride(0), ctypes.c_void_p(sigma.data_ptr()),
+                         float(trunc_tol), ctypes.c_void_p(info.data_ptr()),
+                         ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
+    _check(st, "svqb")
+    return Z, sigma, info
+
+
+def qless_lstsq_finish(Rt, x=None, resid=None, info=None):
+    """x and |rho| from R([A b]) on the device (back substitution)."""
+    import torch
+    Rt, k, k2, ldr = _matrix(Rt, "Rt")
+    n = k - 1
+    dev = Rt.device
+    with torch.cuda.device(dev):
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=dev)
+        if resid is None:
+            resid = torch.empty(1, dtype=torch.float64, device=dev)
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        st = load().qless_lstsq_finish(ctypes.c_void_p(Rt.data_ptr()), n, ldr, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(info.data_ptr()),
+                                       _stream(dev))
+    _check(st, "qless_lstsq_finish")
+    return x, resid, info
+
+
+# ------------------------------------------------------------------ timing
+
+def timing_enable(on: bool = True) -> None:
+    _check(load().qless_timing_enable(1 if on else 0), "qless_timing_enable")
+
+
+def timing_reset() -> None:
+    _check(load().qless_timing_reset(), "qless_timing_reset")
+
+
+def timing_read(kernel: str) -> tuple[float, int]:
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(load().qless_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "qless_timing_read")
+    return ms.value, cnt.value

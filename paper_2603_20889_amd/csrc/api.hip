@@ -1,0 +1,183 @@
+// C-ABI of libqless: argument validation, workspace sizing and dispatch.
+// Every entry point validates on the host before any HIP call that could
+// launch work, so argument errors are testable without a GPU.
+#include <mutex>
+#include <string.h>
+#include <vector>
+
+#include "qless_internal.h"
+
+namespace qless {
+
+// ------------------------------------------------------------ device info
+
+const DeviceInfo& current_device_info() {
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1);
+    DeviceInfo& d = cache[dev];
+    if (d.device < 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;  // MI355X
+        d.num_cus = cus;
+        d.device = dev;
+    }
+    return d;
+}
+
+// ----------------------------------------------------------------- timing
+
+namespace {
+struct TimingSlot {
+    std::vector<hipEvent_t> begin, end;
+    size_t used = 0;
+    double total_ms = 0.0;
+    int64_t count = 0;
+};
+bool g_timing = false;
+TimingSlot g_slots[kTimeSlots];
+const char* const g_slot_names[kTimeSlots] = {"tsqr_stage1", "gram"};
+}  // namespace
+
+void timing_begin(int which, hipStream_t stream) {
+    if (!g_timing) return;
+    TimingSlot& s = g_slots[which];
+    if (s.used == s.begin.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+        s.begin.push_back(a);
+        s.end.push_back(b);
+    }
+    (void)hipEventRecord(s.begin[s.used], stream);
+}
+
+void timing_end(int which, hipStream_t stream) {
+    if (!g_timing) return;
+    TimingSlot& s = g_slots[which];
+    if (s.used >= s.begin.size()) return;
+    (void)hipEventRecord(s.end[s.used], stream);
+    ++s.used;
+}
+
+static void timing_collect(TimingSlot& s) {
+    for (size_t i = 0; i < s.used; ++i) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(s.end[i]) == hipSuccess &&
+            hipEventElapsedTime(&ms, s.begin[i], s.end[i]) == hipSuccess) {
+            s.total_ms += ms;
+            ++s.count;
+        }
+    }
+    s.used = 0;
+}
+
+}  // namespace qless
+
+using namespace qless;
+
+extern "C" {
+
+const char* qless_status_string(int status) {
+    switch (status) {
+        case QLESS_OK: return "QLESS_OK";
+        case QLESS_ERR_ARG: return "QLESS_ERR_ARG: invalid argument";
+        case QLESS_ERR_UNSUPPORTED: return "QLESS_ERR_UNSUPPORTED: n exceeds QLESS_MAX_N (64)";
+        case QLESS_ERR_WORKSPACE: return "QLESS_ERR_WORKSPACE: workspace missing, misaligned or too small";
+        case QLESS_ERR_HIP: return "QLESS_ERR_HIP: HIP runtime or launch failure";
+        default: return "unknown qless status";
+    }
+}
+
+const char* qless_version(void) { return "qless 0.1 gfx950"; }
+
+static int check_matrix_args(const void* X, int64_t m, int64_t n, int64_t ldx, const void* R, int64_t ldr) {
+    if (n < 1 || m < 0) return QLESS_ERR_ARG;
+    if (n > QLESS_MAX_N) return QLESS_ERR_UNSUPPORTED;
+    if (R == nullptr || ldr < n) return QLESS_ERR_ARG;
+    if (m > 0 && (X == nullptr || ldx < n)) return QLESS_ERR_ARG;
+    return QLESS_OK;
+}
+
+static int check_work(const void* work, size_t have, size_t need) {
+    if (need == 0) return QLESS_OK;
+    if (work == nullptr || (reinterpret_cast<uintptr_t>(work) & 255u) != 0 || have < need)
+        return QLESS_ERR_WORKSPACE;
+    return QLESS_OK;
+}
+
+size_t qless_workspace_bytes(int method, int64_t m, int64_t n) {
+    if (n < 1 || n > QLESS_MAX_N || m < 0) return 0;
+    const DeviceInfo& d = current_device_info();
+    switch (method) {
+        case QLESS_METHOD_TSQR: return make_tsqr_plan(m, n, d.num_cus).work_bytes;
+        default: return 0;
+    }
+}
+
+int qless_tsqr_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr, void* work,
+                 size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, R, ldr);
+    if (st != QLESS_OK) return st;
+    const DeviceInfo& d = current_device_info();
+    TsqrPlan plan = make_tsqr_plan(m, n, d.num_cus);
+    st = check_work(work, work_bytes, plan.work_bytes);
+    if (st != QLESS_OK) return st;
+    return launch_tsqr(X, m, n, ldx, R, ldr, work, plan, stream) == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int cholqr2_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr, int32_t* info,
+              void* work, size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, R, ldr);
+    if (st != QLESS_OK) return st;
+    (void)info; (void)work; (void)work_bytes; (void)stream;
+    return QLESS_ERR_UNSUPPORTED;
+}
+
+int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_or_R, int64_t ldz,
+         double* sigma, double trunc_tol, int32_t* info, void* work, size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, Z_or_R, ldz);
+    if (st != QLESS_OK) return st;
+    (void)out; (void)sigma; (void)trunc_tol; (void)info; (void)work; (void)work_bytes; (void)stream;
+    return QLESS_ERR_UNSUPPORTED;
+}
+
+int qless_lstsq_finish(const double* Rt, int64_t n, int64_t ldr, double* x, double* resid, int32_t* info,
+                       hipStream_t stream) {
+    if (Rt == nullptr || x == nullptr || n < 1 || ldr < n + 1) return QLESS_ERR_ARG;
+    if (n + 1 > QLESS_MAX_N) return QLESS_ERR_UNSUPPORTED;
+    (void)resid; (void)info; (void)stream;
+    return QLESS_ERR_UNSUPPORTED;
+}
+
+int qless_timing_enable(int on) {
+    g_timing = (on != 0);
+    return QLESS_OK;
+}
+
+int qless_timing_reset(void) {
+    for (auto& s : g_slots) {
+        timing_collect(s);
+        s.total_ms = 0.0;
+        s.count = 0;
+    }
+    return QLESS_OK;
+}
+
+int qless_timing_read(const char* kernel, double* total_ms, int64_t* count) {
+    if (kernel == nullptr || total_ms == nullptr || count == nullptr) return QLESS_ERR_ARG;
+    for (int i = 0; i < kTimeSlots; ++i)
+        if (strcmp(kernel, g_slot_names[i]) == 0) {
+            timing_collect(g_slots[i]);
+            *total_ms = g_slots[i].total_ms;
+            *count = g_slots[i].count;
+            return QLESS_OK;
+        }
+    return QLESS_ERR_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports what include/qless.h declares, and
+rejects bad arguments on the host before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2603_20889_amd as q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_entry_points():
+    decl = declared_functions()
+    for name in ("qless_tsqr_r", "cholqr2_r", "svqb", "qless_workspace_bytes", "qless_lstsq_finish"):
+        assert name in decl
+
+
+def test_library_exports_every_declared_symbol():
+    lib = q.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(q.EXPORTED) <= set(declared_functions())
+
+
+def test_status_strings_and_version():
+    assert q.version().startswith("qless")
+    for st in (0, -1, -2, -3, -4):
+        assert q.status_string(st).startswith("QLESS_")
+
+
+NULL = ctypes.c_void_p(0)
+FAKE = ctypes.c_void_p(0x100000)   # never dereferenced: every case fails validation first
+
+
+@pytest.mark.parametrize("m,n,ldx,R,ldr,expect", [
+    (100, 0, 8, FAKE, 8, q.QLESS_ERR_ARG),
+    (-1, 4, 4, FAKE, 4, q.QLESS_ERR_ARG),
+    (100, 65, 65, FAKE, 65, q.QLESS_ERR_UNSUPPORTED),
+    (100, 8, 7, FAKE, 8, q.QLESS_ERR_ARG),
+    (100, 8, 8, NULL, 8, q.QLESS_ERR_ARG),
+    (100, 8, 8, FAKE, 7, q.QLESS_ERR_ARG),
+])
+def test_tsqr_argument_errors(m, n, ldx, R, ldr, expect):
+    st = q.load().qless_tsqr_r(FAKE, m, n, ldx, R, ldr, NULL, 0, NULL)
+    assert st == expect
+
+
+def test_tsqr_null_x_with_rows_is_an_error():
+    assert q.load().qless_tsqr_r(NULL, 10, 4, 4, FAKE, 4, NULL, 0, NULL) == q.QLESS_ERR_ARG
+
+
+def test_tsqr_workspace_errors():
+    lib = q.load()
+    need = q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 10_000_000, 8)
+    assert need > 0
+    assert lib.qless_tsqr_r(FAKE, 10_000_000, 8, 8, FAKE, 8, NULL, need, NULL) == q.QLESS_ERR_WORKSPACE
+    assert lib.qless_tsqr_r(FAKE, 10_000_000, 8, 8, FAKE, 8, FAKE, need - 1, NULL) == q.QLESS_ERR_WORKSPACE
+    mis = ctypes.c_void_p(0x100008)
+    assert lib.qless_tsqr_r(FAKE, 10_000_000, 8, 8, FAKE, 8, mis, need, NULL) == q.QLESS_ERR_WORKSPACE
+
+
+def test_workspace_query_rejects_bad_sizes():
+    assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 100, 0) == 0
+    assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 100, 65) == 0
+    assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, -5, 4) == 0
+    assert q.qless_workspace_bytes(99, 100, 4) == 0
+
+
+def test_lstsq_argument_errors():
+    lib = q.load()
+    assert lib.qless_lstsq_finish(NULL, 3, 4, FAKE, NULL, NULL, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_lstsq_finish(FAKE, 3, 3, FAKE, NULL, NULL, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_lstsq_finish(FAKE, 0, 4, FAKE, NULL, NULL, NULL) == q.QLESS_ERR_ARG
+
+
+def test_timing_read_rejects_unknown_kernel():
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    assert q.load().qless_timing_read(b"nope", ctypes.byref(ms), ctypes.byref(cnt)) == q.QLESS_ERR_ARG

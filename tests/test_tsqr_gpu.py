@@ -1,0 +1,159 @@
+"""GPU parity of qless_tsqr_r (Alg. 2-4) against the CPU Householder oracle.
+
+Bar (element-wise comparison of the full R on identical seeded inputs):
+e_R = ||R - R_oracle||_F / ||R_oracle||_F <= 1e-12 for kappa <= 1e4, and the
+Gram residual ||X^T X - R^T R||_F / ||X||_2^2 <= 1e-13 (X^T X from Dot2).
+At full benchmark sizes, where the oracle is too slow, the known-answer
+property R(Q0 R0) = R0 is checked instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_20889_amd as q
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+E_R = 1e-12
+E_G = 1e-13
+
+
+def run(X_np, dev, ldx_pad=0):
+    m, n = X_np.shape
+    if ldx_pad:
+        buf = torch.zeros((m, n + ldx_pad), dtype=torch.float64, device=dev)
+        buf[:, :n] = torch.from_numpy(X_np).to(dev)
+        Xd = buf[:, :n]
+    else:
+        Xd = torch.from_numpy(np.ascontiguousarray(X_np)).to(dev)
+    R = q.qless_tsqr_r(Xd)
+    torch.cuda.synchronize(dev)
+    return R.cpu().numpy()
+
+
+def check(X, R, tol_r=E_R, tol_g=E_G):
+    Ro = oracle.householder_r(X)
+    e_r = oracle.rel_err_r(R, Ro)
+    e_g = oracle.gram_residual(X, R)
+    assert np.all(np.tril(R, -1) == 0.0)
+    assert np.all(np.diag(R) >= 0.0)
+    assert not np.signbit(R[np.triu_indices(R.shape[0])][R[np.triu_indices(R.shape[0])] == 0]).any()
+    assert e_r <= tol_r, "e_R=%g" % e_r
+    assert e_g <= tol_g, "e_G=%g" % e_g
+    return e_r, e_g
+
+
+def test_config1_100000x4(gpu):
+    X = wl.config1()
+    print("case config1", flush=True)
+    check(X, run(X, gpu))
+
+
+SHAPES = [
+    (1, 1), (1, 4), (3, 8), (7, 8), (63, 1), (64, 2), (65, 3), (511, 4), (513, 5), (1000, 6), (4097, 7),
+    (9999, 8), (12345, 9), (20000, 10), (3000, 12), (40001, 13), (50000, 16), (777, 17), (20000, 20),
+    (33333, 24), (10000, 31), (20000, 32), (5000, 33), (8000, 40), (6000, 48), (4000, 63), (10000, 64),
+    (300_001, 8), (262_144, 16),
+]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_random_shapes(gpu, m, n):
+    print("case shape m=%d n=%d" % (m, n), flush=True)
+    X = wl.gaussian(m, n, seed=m * 7 + n)
+    check(X, run(X, gpu))
+
+
+def test_empty_matrix(gpu):
+    R = q.qless_tsqr_r(torch.zeros((0, 5), dtype=torch.float64, device=gpu))
+    torch.cuda.synchronize(gpu)
+    assert torch.equal(R.cpu(), torch.zeros((5, 5), dtype=torch.float64))
+
+
+@pytest.mark.parametrize("n,k", [(4, 4), (8, 4), (8, 8), (16, 4), (16, 8), (32, 4), (64, 4)])
+def test_known_r_conditioning(gpu, n, k):
+    print("case known-R n=%d k=%d" % (n, k), flush=True)
+    X, R0 = wl.known_r(60_000, n, wl.logspace_sigma(n, k), seed=900 + 10 * n + k)
+    R = run(X, gpu)
+    if k <= 4:
+        check(X, R)
+        assert oracle.rel_err_r(R, R0) <= E_R
+    else:  # kappa = 1e8: beyond the 1e4 bar; still backward stable
+        assert oracle.gram_residual(X, R) <= E_G
+        assert oracle.rel_err_r(R, oracle.householder_r(X)) <= 1e-10
+
+
+@pytest.mark.parametrize("m,n,pad", [(10000, 8, 3), (5000, 5, 1), (3000, 16, 16)])
+def test_leading_dimension(gpu, m, n, pad):
+    X = wl.gaussian(m, n, seed=5 + pad)
+    check(X, run(X, gpu, ldx_pad=pad))
+
+
+def test_zero_column_and_rank_deficiency(gpu):
+    X = wl.gaussian(30000, 8, seed=3)
+    X[:, 5] = 0.0
+    R = run(X, gpu)
+    assert np.all(R[:, 5] == 0.0)
+    assert oracle.gram_residual(X, R) <= E_G
+    Y = wl.gaussian(30000, 6, seed=4)
+    Y[:, 4] = Y[:, 1]
+    R = run(Y, gpu)
+    assert abs(R[4, 4]) <= 1e-12 * np.abs(R).max()
+    assert oracle.gram_residual(Y, R) <= E_G
+
+
+def test_all_zero_matrix(gpu):
+    R = run(np.zeros((5000, 7)), gpu)
+    assert np.array_equal(R, np.zeros((7, 7)))
+
+
+def test_deterministic_bitwise(gpu):
+    X = torch.from_numpy(wl.gaussian(200_000, 12, seed=8)).to(gpu)
+    R1 = q.qless_tsqr_r(X)
+    R2 = q.qless_tsqr_r(X)
+    torch.cuda.synchronize(gpu)
+    assert torch.equal(R1, R2)
+
+
+def test_power_of_two_scaling_bitwise(gpu):
+    X = wl.gaussian(100_000, 8, seed=17)
+    R1 = run(X, gpu)
+    R2 = run(np.ldexp(X, -7), gpu)
+    assert np.array_equal(R2, np.ldexp(R1, -7))
+
+
+def test_stacking_identity_on_gpu(gpu):
+    """Alg. 2: R(X) = R([R(X_1); R(X_2); R(X_3)]) with every factor on the GPU."""
+    X = wl.gaussian(90_000, 10, seed=23)
+    parts = np.split(X, [1000, 51_000])
+    Rs = [run(p, gpu) for p in parts]
+    Rstack = run(np.vstack(Rs), gpu)
+    assert oracle.rel_err_r(Rstack, oracle.householder_r(X)) <= E_R
+
+
+@pytest.mark.slow
+def test_config2_full_size_known_r(gpu):
+    """5e7 x 8, kappa = 1e4, in the benchmark's launch configuration."""
+    print("case config2 full size", flush=True)
+    X, R0 = wl.config2(device=gpu)
+    R = q.qless_tsqr_r(X)
+    torch.cuda.synchronize(gpu)
+    R = R.cpu().numpy()
+    del X
+    torch.cuda.empty_cache()
+    assert oracle.rel_err_r(R, R0) <= E_R
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [1, 16, 64])
+def test_config3_full_size_known_r(gpu, n):
+    print("case config3 full size n=%d" % n, flush=True)
+    X, R0 = wl.config3(n, 4, device=gpu)
+    R = q.qless_tsqr_r(X)
+    torch.cuda.synchronize(gpu)
+    R = R.cpu().numpy()
+    del X
+    torch.cuda.empty_cache()
+    assert oracle.rel_err_r(R, R0) <= E_R
