@@ -96,6 +96,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--m", type=int, default=50_000_000)
     ap.add_argument("--n", type=int, default=8)
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (torch) for HBM-counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -180,6 +183,31 @@ def main() -> int:
                                          "single-threaded oracle" % (m, n)}
         out["accuracy"]["e_R_vs_oracle"] = float(np.linalg.norm(R.cpu().numpy() - Ro) / np.linalg.norm(Ro))
         del Xh
+
+    if not args.no_compare:
+        comp = {}
+        for name, fn in (("cholqr2", lambda: q.cholqr2_r(X)), ("svqb2", lambda: q.svqb(X, out=q.QLESS_SVQB_R))):
+            log("compare %s" % name)
+            c_ms, _ = time_calls(fn, max(5, args.steps // 3), 2)
+            res = fn()
+            torch.cuda.synchronize()
+            Rc = res[0].cpu().numpy()
+            comp[name] = {"ms": round(c_ms, 5), "GBps": round(gram2_bytes(m, n) / (c_ms * 1e-3) / 1e9, 1),
+                          "e_R_vs_R0": float(np.linalg.norm(Rc - R0) / np.linalg.norm(R0)),
+                          "info": int(res[-1].item())}
+            log(json.dumps(comp[name]))
+        comp["tsqr_speedup_vs_svqb2"] = round(comp["svqb2"]["ms"] / ms, 3)
+        comp["tsqr_speedup_vs_cholqr2"] = round(comp["cholqr2"]["ms"] / ms, 3)
+        out["compare"] = comp
+
+    if args.calib_copy:
+        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 8
+        del src, dst
 
     del X, work
     torch.cuda.empty_cache()

@@ -76,6 +76,39 @@ static void timing_collect(TimingSlot& s) {
     s.used = 0;
 }
 
+// Workspace of the Gram-based forms: k partial Gram matrices, C, four n x n
+// work matrices, one n-vector and an int status word, each 256-byte aligned.
+struct GramWork {
+    double* Cpart = nullptr;
+    double* C = nullptr;
+    double *A1 = nullptr, *A2 = nullptr, *A3 = nullptr, *A4 = nullptr;
+    double* vec = nullptr;
+    int* iw = nullptr;
+    size_t bytes = 0;
+};
+
+GramWork gram_work_layout(const GramPlan& gp, int64_t n, void* base) {
+    GramWork w;
+    char* b = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t nbytes) -> char* {
+        char* p = b ? b + off : nullptr;
+        off += align_up(nbytes, 256);
+        return p;
+    };
+    const size_t sq = (size_t)(n * n) * sizeof(double);
+    w.Cpart = reinterpret_cast<double*>(take(gp.part_bytes));
+    w.C = reinterpret_cast<double*>(take(sq));
+    w.A1 = reinterpret_cast<double*>(take(sq));
+    w.A2 = reinterpret_cast<double*>(take(sq));
+    w.A3 = reinterpret_cast<double*>(take(sq));
+    w.A4 = reinterpret_cast<double*>(take(sq));
+    w.vec = reinterpret_cast<double*>(take((size_t)n * sizeof(double)));
+    w.iw = reinterpret_cast<int*>(take(sizeof(int)));
+    w.bytes = off;
+    return w;
+}
+
 }  // namespace qless
 
 using namespace qless;
@@ -115,6 +148,8 @@ size_t qless_workspace_bytes(int method, int64_t m, int64_t n) {
     const DeviceInfo& d = current_device_info();
     switch (method) {
         case QLESS_METHOD_TSQR: return make_tsqr_plan(m, n, d.num_cus).work_bytes;
+        case QLESS_METHOD_CHOLQR2:
+        case QLESS_METHOD_SVQB: return gram_work_layout(make_gram_plan(m, n, d.num_cus), n, nullptr).bytes;
         default: return 0;
     }
 }
@@ -134,24 +169,58 @@ int cholqr2_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int
               void* work, size_t work_bytes, hipStream_t stream) {
     int st = check_matrix_args(X, m, n, ldx, R, ldr);
     if (st != QLESS_OK) return st;
-    (void)info; (void)work; (void)work_bytes; (void)stream;
-    return QLESS_ERR_UNSUPPORTED;
+    const DeviceInfo& d = current_device_info();
+    GramPlan gp = make_gram_plan(m, n, d.num_cus);
+    GramWork gw = gram_work_layout(gp, n, work);
+    st = check_work(work, work_bytes, gw.bytes);
+    if (st != QLESS_OK) return st;
+    const int ni = (int)n;
+    hipError_t e = launch_gram(X, m, n, ldx, nullptr, gw.Cpart, gw.C, gp, stream);      // C = X^T X
+    if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, gw.A1, gw.A2, gw.iw, 0, stream);  // R1, R1^{-1}
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, gw.A2, gw.Cpart, gw.C, gp, stream); // (X/R1)^T (X/R1)
+    if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, gw.A3, gw.A4, gw.iw, ni, stream); // R2
+    if (e == hipSuccess) e = launch_trmm_out(gw.A3, gw.A1, ni, R, ldr, gw.iw, stream);   // R = R2 R1
+    if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 
 int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_or_R, int64_t ldz,
          double* sigma, double trunc_tol, int32_t* info, void* work, size_t work_bytes, hipStream_t stream) {
     int st = check_matrix_args(X, m, n, ldx, Z_or_R, ldz);
     if (st != QLESS_OK) return st;
-    (void)out; (void)sigma; (void)trunc_tol; (void)info; (void)work; (void)work_bytes; (void)stream;
-    return QLESS_ERR_UNSUPPORTED;
+    if (out != QLESS_SVQB_R && out != QLESS_SVQB_QZ) return QLESS_ERR_ARG;
+    if (!(trunc_tol > 0.0)) trunc_tol = (double)n * 2.220446049250313e-16;
+    const DeviceInfo& d = current_device_info();
+    GramPlan gp = make_gram_plan(m, n, d.num_cus);
+    GramWork gw = gram_work_layout(gp, n, work);
+    st = check_work(work, work_bytes, gw.bytes);
+    if (st != QLESS_OK) return st;
+    const int ni = (int)n;
+    double* U1 = gw.A1;
+    double* D1 = gw.A2;
+    double* Zt = gw.A3;
+    double* lam1 = gw.vec;
+    double* zdst = (out == QLESS_SVQB_QZ) ? Z_or_R : Zt;
+    const int64_t zld = (out == QLESS_SVQB_QZ) ? ldz : n;
+    hipError_t e = launch_gram(X, m, n, ldx, nullptr, gw.Cpart, gw.C, gp, stream);
+    if (e == hipSuccess)
+        e = launch_svqb_eig(gw.C, ni, trunc_tol, 1, U1, lam1, D1, sigma, nullptr, 0, gw.iw, stream);
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, D1, gw.Cpart, gw.C, gp, stream);
+    if (e == hipSuccess)
+        e = launch_svqb_eig(gw.C, ni, trunc_tol, 0, U1, lam1, nullptr, nullptr, zdst, zld, gw.iw, stream);
+    if (e == hipSuccess && out == QLESS_SVQB_R) {
+        TsqrPlan tp = make_tsqr_plan(n, n, d.num_cus);   // one wavefront, no tree
+        e = launch_tsqr(Zt, n, n, n, Z_or_R, ldz, nullptr, tp, stream);
+    }
+    if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 
 int qless_lstsq_finish(const double* Rt, int64_t n, int64_t ldr, double* x, double* resid, int32_t* info,
                        hipStream_t stream) {
     if (Rt == nullptr || x == nullptr || n < 1 || ldr < n + 1) return QLESS_ERR_ARG;
     if (n + 1 > QLESS_MAX_N) return QLESS_ERR_UNSUPPORTED;
-    (void)resid; (void)info; (void)stream;
-    return QLESS_ERR_UNSUPPORTED;
+    return launch_lstsq(Rt, (int)n, ldr, x, resid, info, stream) == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 
 int qless_timing_enable(int on) {

@@ -13,6 +13,8 @@ namespace qless {
 
 constexpr int kWave = 64;
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 // ------------------------------------------------------------ wave exchange
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -46,11 +48,12 @@ __device__ __forceinline__ void swap16_f64(double v, double& first, double& seco
 }
 
 // DPP move of a double: every lane receives the value of the lane selected by
-// the DPP control word `ctrl` (all rows and banks enabled).
+// the DPP control word `ctrl` (all rows and banks enabled, every source lane
+// valid for the patterns used here, so no "old" value is needed).
 template <int ctrl>
 __device__ __forceinline__ double dpp_f64(double v) {
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -75,6 +78,109 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     v = v + dpp_f64<kDppXor2>(v);
     v = v + dpp_f64<kDppXor1>(v);
     return v;
+}
+
+// ---------------------------------------------- transposed multi-value sum
+//
+// Sum K per-lane values p[0..K-1] over the 64 lanes at the cost of about
+// 1.5 exchanges per value instead of six: each of the six pairing stages
+// (lane bit 5, 4, 3, 2, 1, 0 -- partners as in wave_sum_f64) halves the
+// number of live slots.  For S live slots, slot t < S/2 is paired with slot
+// t + S/2: the lane whose stage bit is 0 keeps slot t, its partner keeps
+// slot t + S/2, and each adds the other's copy of the slot it keeps; an odd
+// leftover slot is summed in both lanes.  Stages on bits 5 and 4 use one
+// v_permlane32/16_swap per 32-bit half, which moves both slots at once; the
+// DPP stages select what to send and keep.  After the six stages each lane
+// holds the full sum of exactly one value in p[0]; which one is a
+// compile-time function of the lane id (red_origin), so red_locate gives a
+// lane to read value v from.
+
+constexpr int red_next(int S) { return S >= 2 ? S / 2 + (S & 1) : 1; }
+
+// Original value index held in p[0] by `lane` after the six stages.
+constexpr int red_origin(int K, int lane) {
+    int S[7] = {K, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < 6; ++s) S[s + 1] = red_next(S[s]);
+    int t = 0;
+    for (int s = 5; s >= 0; --s) {
+        const int Ss = S[s];
+        if (Ss >= 2) {
+            const int P = Ss / 2;
+            if (t < P) t = ((lane >> (5 - s)) & 1) ? t + P : t;
+            else t = 2 * P;
+        }
+    }
+    return t;
+}
+
+constexpr int red_locate(int K, int v) {
+    for (int l = 0; l < 64; ++l)
+        if (red_origin(K, l) == v) return l;
+    return -1;
+}
+
+template <int STAGE>
+__device__ __forceinline__ double red_pair(double a, double b, int lane) {
+    if constexpr (STAGE == 0 || STAGE == 1) {
+        int2 lo, hi;
+        if constexpr (STAGE == 0) {
+            auto l = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+            auto h = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+            lo = make_int2(l[0], l[1]);
+            hi = make_int2(h[0], h[1]);
+        } else {
+            auto l = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+            auto h = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+            lo = make_int2(l[0], l[1]);
+            hi = make_int2(h[0], h[1]);
+        }
+        return __hiloint2double(hi.x, lo.x) + __hiloint2double(hi.y, lo.y);
+    } else {
+        constexpr int bit = 5 - STAGE;
+        constexpr int ctrl = STAGE == 2 ? kDppRor8 : STAGE == 3 ? kDppMirror8 : STAGE == 4 ? kDppXor2 : kDppXor1;
+        const bool up = (lane >> bit) & 1;
+        const double send = up ? a : b;
+        const double keep = up ? b : a;
+        return keep + dpp_f64<ctrl>(send);
+    }
+}
+
+template <int STAGE>
+__device__ __forceinline__ double red_all(double v) {
+    if constexpr (STAGE == 0 || STAGE == 1) {
+        double a, b;
+        if constexpr (STAGE == 0) swap32_f64(v, a, b);
+        else swap16_f64(v, a, b);
+        return a + b;
+    } else {
+        constexpr int ctrl = STAGE == 2 ? kDppRor8 : STAGE == 3 ? kDppMirror8 : STAGE == 4 ? kDppXor2 : kDppXor1;
+        return v + dpp_f64<ctrl>(v);
+    }
+}
+
+template <int S, int STAGE>
+__device__ __forceinline__ void red_stages(double* p, int lane) {
+    if constexpr (STAGE < 6) {
+        if constexpr (S >= 2) {
+            constexpr int P = S / 2;
+#pragma unroll
+            for (int t = 0; t < P; ++t) p[t] = red_pair<STAGE>(p[t], p[t + P], lane);
+            if constexpr (S & 1) p[P] = red_all<STAGE>(p[2 * P]);
+            red_stages<P + (S & 1), STAGE + 1>(p, lane);
+        } else {
+            p[0] = red_all<STAGE>(p[0]);
+            red_stages<1, STAGE + 1>(p, lane);
+        }
+    }
+}
+
+// Sum p[0..K-1] over the wavefront; on return tot[v] is the (uniform) total
+// of value v in every lane.
+template <int K>
+__device__ __forceinline__ void wave_sum_multi(double* p, double* tot, int lane) {
+    red_stages<K, 0>(p, lane);
+#pragma unroll
+    for (int v = 0; v < K; ++v) tot[v] = readlane_f64(p[0], red_locate(K, v));
 }
 
 // ------------------------------------------------------------- host plans
@@ -109,12 +215,47 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus);
 hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R,
                        int64_t ldr, void* work, const TsqrPlan& plan, hipStream_t stream);
 
+// Plan of a Gram pass: wavefront count and rows per wavefront.
+struct GramPlan {
+    int npad = 0;              // padded column count (power of two)
+    int64_t rows_per_wave = 0;
+    int64_t k = 0;             // wavefronts = partial Gram matrices
+    size_t part_bytes = 0;     // bytes of the k partials
+};
+
+GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus);
+
+// C = (X M)^T (X M) (M == nullptr: C = X^T X), via k wavefront partials in
+// Cpart and a fixed-order sum into C (n x n, ld n).
+hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, double* Cpart,
+                       double* C, const GramPlan& plan, hipStream_t stream);
+
+// Small n x n device steps (small.hip); every kernel runs as one workgroup.
+// Upper Cholesky C = R^T R with R^{-1}; sets *info = info_base + j on a
+// non-positive pivot in column j (1-based) unless *info is already non-zero.
+hipError_t launch_chol_inv(const double* C, int n, double* R, double* Rinv, int* info, int info_base,
+                           hipStream_t stream);
+// out = R2 * R1 (upper triangular product), ld ldo; NaN everywhere if *info != 0.
+hipError_t launch_trmm_out(const double* R2, const double* R1, int n, double* out, int64_t ldo, const int* info,
+                           hipStream_t stream);
+// Symmetric eigendecomposition (parallel cyclic Jacobi), eigenvalues decreasing.
+//   first pass (first != 0): D = U L^{-1/2} (truncated), U1 and lam1 kept,
+//   sigma (may be null) = sqrt(lam); second pass: Z = L2^{1/2} U2^T L1^{1/2} U1^T.
+// *ntrunc accumulates the number of truncated eigenvalues (first pass resets it).
+hipError_t launch_svqb_eig(const double* C, int n, double trunc_tol, int first, double* U1, double* lam1,
+                           double* D, double* sigma, double* Z, int64_t ldz, int* ntrunc, hipStream_t stream);
+// x = RA^{-1} z and |rho| from Rt = R([A b]) ((n+1) x (n+1), ld ldr).
+hipError_t launch_lstsq(const double* Rt, int n, int64_t ldr, double* x, double* resid, int* info,
+                        hipStream_t stream);
+// Copy of a device int (used to publish an internal info word).
+hipError_t launch_copy_int(const int* src, int* dst, hipStream_t stream);
+
 // Benchmark timing hooks (api.hip).
 void timing_begin(int which, hipStream_t stream);
 void timing_end(int which, hipStream_t stream);
 enum { kTimeTsqrStage1 = 0, kTimeGram = 1, kTimeSlots = 2 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace qless

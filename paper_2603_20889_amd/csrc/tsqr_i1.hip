@@ -1,0 +1,22 @@
+// Kernel instances of the TSQR fold for n = 1, 2, 3, 4 (one file per group so
+// the instances compile in parallel).
+#include "tsqr_kernels.h"
+
+namespace qless {
+hipError_t launch_fold_np1(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<1, 64>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np2(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<2, 32>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np3(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<3, 21>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<4, 16>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+}  // namespace qless

@@ -1,0 +1,22 @@
+// Kernel instances of the TSQR fold for n = 5, 6, 7, 8 (one file per group so
+// the instances compile in parallel).
+#include "tsqr_kernels.h"
+
+namespace qless {
+hipError_t launch_fold_np5(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<5, 12>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np6(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<6, 10>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np7(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<7, 9>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np8(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<8, 8>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+}  // namespace qless

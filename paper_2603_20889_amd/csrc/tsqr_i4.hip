@@ -1,0 +1,18 @@
+// Kernel instances of the TSQR fold for n = 24, 32, 40 (one file per group so
+// the instances compile in parallel).
+#include "tsqr_kernels.h"
+
+namespace qless {
+hipError_t launch_fold_np24(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<24, 21>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np32(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<32, 16>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np40(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<40, 12>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+}  // namespace qless

@@ -1,0 +1,14 @@
+// Kernel instances of the TSQR fold for n = 48, 56 (one file per group so
+// the instances compile in parallel).
+#include "tsqr_kernels.h"
+
+namespace qless {
+hipError_t launch_fold_np48(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<48, 10>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+hipError_t launch_fold_np56(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+                          int64_t ldy, int fin, hipStream_t s) {
+    return tsqr_detail::launch_fold<56, 9>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+}
+}  // namespace qless

@@ -1,0 +1,313 @@
+// Q-less Householder TSQR kernels for gfx950 (paper Alg. 2-4).
+//
+// Stage 1 (Alg. 2, first call; Alg. 3): the rows of X are split into k
+// contiguous blocks, one per wavefront.  A wavefront streams its block in
+// panels and keeps the running triangle R of the rows seen so far in LDS
+// (wavefront-private; broadcast reads, one-lane writes).  Each panel W is
+// folded in by the structured Householder QR of [R; W] (Alg. 4 without the
+// column pairing): the reflector of column j pivots on R_jj and spans column
+// j of W, so it touches only row j of R and the panel.  Q and the reflectors
+// are never stored.  At the end the wavefront writes its R_i (n x n) into
+// the stacked buffer Y.
+//
+// Two register layouts of a panel:
+//   n <= 16 (tsqr_fold_kernel): lane l holds RPL = 64/n full rows
+//     (l, l+64, ...), i.e. 64 doubles; the K = n - j dot products of step j
+//     are per-lane partial sums reduced over 64 lanes by one transposed
+//     butterfly (wave_sum_multi).
+//   n > 16 (tsqr_fold2d_kernel): 8 row groups x 8 column groups; lane
+//     (rg, cg) holds RPL rows of the columns cg, cg+8, ...; the pivot column
+//     is broadcast inside the row group and the sums run over the 8 row
+//     groups only.
+//
+// Stage 2 (Alg. 2, second call): the stacked triangles are reduced by a tree
+// of the same kernels -- each wavefront of a level treats fan_in consecutive
+// R_i as a tall (fan_in*n) x n matrix -- until one remains; the last launch
+// writes R with its diagonal made non-negative.
+#pragma once
+
+#include "qless_internal.h"
+
+namespace qless {
+namespace tsqr_detail {
+
+
+// Fold one panel for NP <= 16: the column loop is a compile-time recursion so
+// that every register index is a constant.  Step J forms the K = NP - J
+// partial dot products of column J with columns J..NP-1 in each lane, sums
+// all K over the wavefront in one transposed butterfly, and applies the
+// reflector; the scalars (norm, beta, gamma) are wave-uniform.
+template <int NP, int RPL, int J>
+struct FoldStep {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, int lane) {
+        if constexpr (J < NP) {
+            constexpr int K = NP - J;
+            double p[K], tot[K], rj[K];
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) s = fma(x[i][J], x[i][J + t], s);
+                p[t] = s;
+            }
+#pragma unroll
+            for (int t = 0; t < K; ++t) rj[t] = Rw[J * NP + J + t];
+            wave_sum_multi<K>(p, tot, lane);
+            const double alpha = rj[0];
+            const double s = tot[0];
+            if (s != 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, s));
+                const double beta = (alpha >= 0.0) ? -nrm : nrm;
+                const double u0 = alpha - beta;
+                const double gamma = 1.0 / (nrm * (nrm + fabs(alpha)));
+#pragma unroll
+                for (int t = 1; t < K; ++t) {
+                    const double coef = gamma * fma(u0, rj[t], tot[t]);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) x[i][J + t] = fma(-coef, x[i][J], x[i][J + t]);
+                    rj[t] = fma(-coef, u0, rj[t]);
+                }
+                rj[0] = beta;
+                if (lane == 0) {
+#pragma unroll
+                    for (int t = 0; t < K; ++t) Rw[J * NP + J + t] = rj[t];
+                }
+            }
+            FoldStep<NP, RPL, J + 1>::run(x, Rw, lane);
+        }
+    }
+};
+
+template <int NP>
+constexpr int waves_per_block() {
+    return (NP * NP * 8 * 4 <= 65536) ? 4 : 2;
+}
+
+// One kernel for stage 1 and every tree level.
+//   X: rows [0, m) of a row-major matrix with leading dimension ldx, n columns.
+//   Wavefront w owns rows [w*rows_per_wave, min(m, (w+1)*rows_per_wave)).
+//   final == 0: write R_w (n x n, ld n) to Y + w*n*n.
+//   final != 0: (single wavefront) write sign-normalised R to Y with ld ldy.
+template <int NP, int RPL>
+__global__ void __launch_bounds__(64 * waves_per_block<NP>())
+tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int final_write, int buffer_ok) {
+    constexpr int WPB = waves_per_block<NP>();
+    __shared__ double Rsh[WPB][NP * NP];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * WPB + wib;
+    if (w >= nwaves) return;
+    double* Rw = Rsh[wib];
+    for (int e = lane; e < NP * NP; e += kWave) Rw[e] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    for (int64_t base = r_begin; base < r_end; base += (int64_t)kWave * RPL) {
+        double x[RPL][NP];
+        const bool full = base + (int64_t)kWave * RPL <= r_end;
+        if (full && n == NP && buffer_ok) {
+            // interior panel: buffer loads from a resource rebased at the panel,
+            // lane offset in a VGPR, row-stripe offset in an SGPR.
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+            const int vo = lane * (int)(ldx * 8);
+            const int so = (int)(ldx * 8 * kWave);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+#pragma unroll
+                for (int c = 0; c < NP; c += 2) {
+                    if (c + 1 < NP) {
+                        const f64x2 v = __builtin_bit_cast(
+                            f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + c * 8, so * i, 0));
+                        x[i][c] = v[0];
+                        x[i][c + 1] = v[1];
+                    } else {
+                        x[i][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + c * 8, so * i, 0));
+                    }
+                }
+            }
+        } else {
+            // tail panel or padded width: guarded loads, zero fill
+            const int64_t left = r_end - base - lane;   // rows of this lane's stripe still in range
+            const double* x0 = X + (left > 0 ? base + lane : 0) * ldx;
+            const int64_t step = (int64_t)kWave * ldx;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const bool ok = (int64_t)kWave * i < left;
+#pragma unroll
+                for (int c = 0; c < NP; ++c) x[i][c] = (ok && c < n) ? x0[step * i + c] : 0.0;
+            }
+        }
+        FoldStep<NP, RPL, 0>::run(x, Rw, lane);
+    }
+
+    if (lane < n) {
+        const int r = lane;
+        double sgn = 1.0;
+        if (final_write && Rw[r * NP + r] < 0.0) sgn = -1.0;
+        double* out = final_write ? Y + (int64_t)r * ldy : Y + w * (int64_t)n * n + (int64_t)r * n;
+        for (int c = 0; c < n; ++c) {
+            double v = (c >= r) ? Rw[r * NP + c] : 0.0;
+            out[c] = final_write ? sgn * v + 0.0 : v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column-group layout for 16 < n <= 64.  Full rows no longer fit a lane's
+// registers with enough rows per lane to amortise the cross-lane sums, so the
+// 64 lanes form 8 row groups of 8 lanes: lane (rg, cg) holds RPL rows of its
+// row group and the columns c = cg + 8u (u < NP/8).  For column J the pivot
+// column is broadcast inside each row group (ds_swizzle), each lane forms the
+// dot products for its own columns, and the sums run over the 8 row groups
+// only (lane bits 3..5).  Cyclic column ownership keeps every lane busy as J
+// advances.
+constexpr int kG2 = 8;                   // column groups (lanes per row group)
+constexpr int kRG2 = kWave / kG2;        // row groups
+
+template <int CG>
+__device__ __forceinline__ double bcast_in_group8(double v) {
+    constexpr int off = 0x18 | (CG << 5);  // ds_swizzle bitmask mode: lane = (lane & 0x18) | CG
+    int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), off);
+    int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), off);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double sum_over_row_groups(double v) {
+    v = v + dpp_f64<kDppRor8>(v);  // lane bit 3
+    {
+        int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);  // xor 16
+        int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+        v = v + __hiloint2double(hi, lo);
+    }
+    return v + __shfl_xor(v, 32, kWave);  // lane bit 5
+}
+
+template <int NP, int RPL, int J>
+struct FoldStep2D {
+    static constexpr int NC = NP / kG2;
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP / kG2], double* __restrict__ Rw, int lane) {
+        if constexpr (J < NP) {
+            constexpr int cgJ = J % kG2;
+            constexpr int uJ = J / kG2;
+            constexpr int A = NC - uJ;  // live column slots (slot uJ only partly live)
+            const int cg = lane % kG2;
+            double piv[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) piv[i] = bcast_in_group8<cgJ>(x[i][uJ]);
+            double p[A], r[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) t = fma(piv[i], x[i][uJ + a], t);
+                p[a] = t;
+                r[a] = Rw[J * NP + cg + kG2 * (uJ + a)];
+            }
+#pragma unroll
+            for (int a = 0; a < A; ++a) p[a] = sum_over_row_groups(p[a]);
+            const double s = readlane_f64(p[0], cgJ);   // |panel part of column J|^2
+            const double alpha = Rw[J * NP + J];
+            if (s != 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, s));
+                const double beta = (alpha >= 0.0) ? -nrm : nrm;
+                const double u0 = alpha - beta;
+                const double gamma = 1.0 / (nrm * (nrm + fabs(alpha)));
+#pragma unroll
+                for (int a = 0; a < A; ++a) {
+                    const int c = cg + kG2 * (uJ + a);
+                    const bool live = (a > 0) || (c > J);
+                    double coef = gamma * fma(u0, r[a], p[a]);
+                    coef = live ? coef : 0.0;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) x[i][uJ + a] = fma(-coef, piv[i], x[i][uJ + a]);
+                    if (live && lane < kG2) Rw[J * NP + c] = fma(-coef, u0, r[a]);
+                }
+                if (lane == 0) Rw[J * NP + J] = beta;
+            }
+            FoldStep2D<NP, RPL, J + 1>::run(x, Rw, lane);
+        }
+    }
+};
+
+template <int NP, int RPL>
+__global__ void __launch_bounds__(64 * waves_per_block<NP>())
+tsqr_fold2d_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                   int64_t nwaves, double* __restrict__ Y, int64_t ldy, int final_write, int buffer_ok) {
+    constexpr int WPB = waves_per_block<NP>();
+    constexpr int NC = NP / kG2;
+    __shared__ double Rsh[WPB][NP * NP];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * WPB + wib;
+    if (w >= nwaves) return;
+    double* Rw = Rsh[wib];
+    for (int e = lane; e < NP * NP; e += kWave) Rw[e] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const int rg = lane / kG2, cg = lane % kG2;
+
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        double x[RPL][NC];
+        const bool full = base + PANEL <= r_end;
+        if (full && n == NP && buffer_ok) {
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+            const int vo = (int)((rg * ldx + cg) * 8);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+#pragma unroll
+                for (int u = 0; u < NC; ++u)
+                    x[i][u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                             rs, vo, (int)((kRG2 * i * ldx + kG2 * u) * 8), 0));
+        } else {
+            const int64_t left = r_end - base - rg;
+            const double* x0 = X + (left > 0 ? base + rg : 0) * ldx;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const bool ok = (int64_t)kRG2 * i < left;
+#pragma unroll
+                for (int u = 0; u < NC; ++u) {
+                    const int c = cg + kG2 * u;
+                    x[i][u] = (ok && c < n) ? x0[(int64_t)kRG2 * i * ldx + c] : 0.0;
+                }
+            }
+        }
+        FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
+    }
+
+    if (lane < n) {
+        const int r = lane;
+        double sgn = 1.0;
+        if (final_write && Rw[r * NP + r] < 0.0) sgn = -1.0;
+        double* out = final_write ? Y + (int64_t)r * ldy : Y + w * (int64_t)n * n + (int64_t)r * n;
+        for (int c = 0; c < n; ++c) {
+            double v = (c >= r) ? Rw[r * NP + c] : 0.0;
+            out[c] = final_write ? sgn * v + 0.0 : v;
+        }
+    }
+}
+
+template <int NP, int RPL>
+hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                       int64_t nwaves, double* Y, int64_t ldy, int final_write, hipStream_t stream) {
+    constexpr int WPB = waves_per_block<NP>();
+    const int64_t blocks = ceil_div(nwaves, WPB);
+    if constexpr (NP <= 16) {
+        hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream,
+                           X, m, n, ldx, rows_per_wave, nwaves, Y, ldy, final_write,
+                           (int)((int64_t)kWave * RPL * ldx * 8 < 0x7FFFFFFF));
+    } else {
+        hipLaunchKernelGGL((tsqr_fold2d_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream,
+                           X, m, n, ldx, rows_per_wave, nwaves, Y, ldy, final_write,
+                           (int)((int64_t)kRG2 * RPL * ldx * 8 < 0x7FFFFFFF));
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tsqr_detail
+}  // namespace qless
