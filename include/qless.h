@@ -133,6 +133,47 @@ int svqb(const double *X, int64_t m, int64_t n, int64_t ldx, int out,
 int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
                        double *resid, int32_t *info, hipStream_t stream);
 
+/* ------------------------------------------------------------- batched */
+
+/*
+ * Batched Q-less TSQR: many independent matrices of uneven m and n in one
+ * persistent launch (Alg. 2 applied to each).  Descriptor fields follow
+ * qless_tsqr_r: X (device, m x n row-major, ldx >= n; may be NULL when
+ * m == 0), R (device, n x n, ldr >= n), 1 <= n <= QLESS_MAX_N.  With
+ * accumulate != 0 the matrix's current R (any upper-triangular n x n, e.g.
+ * the R of rows seen earlier) is stacked in: the result is R([R_old; X]),
+ * which lets a caller keep a running R over chunks of rows.
+ */
+typedef struct {
+    const double *X;
+    int64_t m, n, ldx;
+    double *R;
+    int64_t ldr;
+    int32_t accumulate;
+} qless_matrix_desc;
+
+/* Opaque host-side plan: tiles every matrix into row ranges of about
+ * tile_bytes (<= 0: 4 MiB) and orders them longest first; waves_per_cu
+ * (<= 0: 8) sets the persistent grid.  The descriptors are copied; their
+ * device pointers must stay valid while the plan is used.  Returns
+ * QLESS_ERR_ARG / QLESS_ERR_UNSUPPORTED for an invalid descriptor. */
+typedef struct qless_batch_plan qless_batch_plan;
+int qless_batch_plan_create(const qless_matrix_desc *descs, int32_t count, int64_t tile_bytes,
+                            int32_t waves_per_cu, qless_batch_plan **plan);
+void qless_batch_plan_destroy(qless_batch_plan *plan);
+/* Device workspace the plan needs (bytes, 256-byte aligned buffer). */
+size_t qless_batch_plan_workspace_bytes(const qless_batch_plan *plan);
+/* Number of row tiles in the plan. */
+int64_t qless_batch_plan_tiles(const qless_batch_plan *plan);
+/* Copy the plan's tables into `work` and zero its counters; synchronises
+ * `stream`.  Call once per workspace before the first qless_tsqr_r_batched. */
+int qless_batch_plan_upload(const qless_batch_plan *plan, void *work, size_t work_bytes, hipStream_t stream);
+/* One launch computing every matrix's R.  Allocates nothing, copies nothing
+ * from the host and leaves the workspace ready for the next call, so it can
+ * be captured in a hipGraph and replayed.  Calls sharing a workspace must not
+ * overlap. */
+int qless_tsqr_r_batched(const qless_batch_plan *plan, void *work, size_t work_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------- timing hooks */
 
 /*

@@ -35,8 +35,16 @@ QLESS_MAX_N = 64
 EXPORTED = (
     "qless_status_string", "qless_version", "qless_workspace_bytes", "qless_tsqr_r",
     "cholqr2_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
-    "qless_timing_read",
+    "qless_timing_read", "qless_batch_plan_create", "qless_batch_plan_destroy",
+    "qless_batch_plan_workspace_bytes", "qless_batch_plan_tiles", "qless_batch_plan_upload",
+    "qless_tsqr_r_batched",
 )
+
+
+class qless_matrix_desc(ctypes.Structure):
+    """Mirror of the C struct qless_matrix_desc."""
+    _fields_ = [("X", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("ldx", ctypes.c_int64),
+                ("R", ctypes.c_void_p), ("ldr", ctypes.c_int64), ("accumulate", ctypes.c_int32)]
 
 
 class QlessError(RuntimeError):
@@ -73,6 +81,19 @@ def load() -> ctypes.CDLL:
     lib.svqb.restype = ctypes.c_int
     lib.qless_lstsq_finish.argtypes = [vp, i64, i64, vp, vp, vp, vp]
     lib.qless_lstsq_finish.restype = ctypes.c_int
+    lib.qless_batch_plan_create.argtypes = [ctypes.POINTER(qless_matrix_desc), i32, i64, i32,
+                                            ctypes.POINTER(ctypes.c_void_p)]
+    lib.qless_batch_plan_create.restype = ctypes.c_int
+    lib.qless_batch_plan_destroy.argtypes = [vp]
+    lib.qless_batch_plan_destroy.restype = None
+    lib.qless_batch_plan_workspace_bytes.argtypes = [vp]
+    lib.qless_batch_plan_workspace_bytes.restype = sz
+    lib.qless_batch_plan_tiles.argtypes = [vp]
+    lib.qless_batch_plan_tiles.restype = i64
+    lib.qless_batch_plan_upload.argtypes = [vp, vp, sz, vp]
+    lib.qless_batch_plan_upload.restype = ctypes.c_int
+    lib.qless_tsqr_r_batched.argtypes = [vp, vp, sz, vp]
+    lib.qless_tsqr_r_batched.restype = ctypes.c_int
     lib.qless_timing_enable.argtypes = [ctypes.c_int]
     lib.qless_timing_enable.restype = ctypes.c_int
     lib.qless_timing_reset.argtypes = []
@@ -217,6 +238,76 @@ def qless_lstsq_finish(Rt, x=None, resid=None, info=None):
                                        _stream(dev))
     _check(st, "qless_lstsq_finish")
     return x, resid, info
+
+
+# ----------------------------------------------------------------- batched
+
+class BatchPlan:
+    """A batched Q-less TSQR over a fixed set of device matrices.
+
+    ``Xs``: list of 2-D float64 GPU tensors (row-major rows, any m >= 0,
+    1 <= n <= 64).  ``Rs``: optional list of n x n output tensors (allocated
+    otherwise).  ``accumulate``: optional list of bools -- where true, the
+    current content of that R is stacked in (R <- R([R; X])).  The plan and
+    its device workspace are built once; ``run()`` enqueues the single
+    persistent launch on the current stream and may be captured in a graph.
+    """
+
+    def __init__(self, Xs, Rs=None, accumulate=None, tile_bytes: int = 0, waves_per_cu: int = 0):
+        import torch
+        if not Xs:
+            raise ValueError("empty batch")
+        self.device = Xs[0].device
+        self.Xs, self.Rs = [], []
+        descs = (qless_matrix_desc * len(Xs))()
+        for i, X in enumerate(Xs):
+            X, m, n, ldx = _matrix(X)
+            if X.device != self.device:
+                raise ValueError("all matrices must be on one device")
+            R = Rs[i] if Rs is not None else torch.zeros((n, n), dtype=torch.float64, device=self.device)
+            self.Xs.append(X)
+            self.Rs.append(R)
+            descs[i] = qless_matrix_desc(X.data_ptr() if m else 0, m, n, ldx, R.data_ptr(), R.stride(0),
+                                         1 if (accumulate is not None and accumulate[i]) else 0)
+        lib = load()
+        self._lib = lib
+        self._plan = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            _check(lib.qless_batch_plan_create(descs, len(Xs), int(tile_bytes), int(waves_per_cu),
+                                               ctypes.byref(self._plan)), "qless_batch_plan_create")
+            self.work_bytes = int(lib.qless_batch_plan_workspace_bytes(self._plan))
+            self.work = torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
+            _check(lib.qless_batch_plan_upload(self._plan, ctypes.c_void_p(self.work.data_ptr()), self.work_bytes,
+                                               _stream(self.device)), "qless_batch_plan_upload")
+        self.tiles = int(lib.qless_batch_plan_tiles(self._plan))
+
+    def run(self):
+        import torch
+        with torch.cuda.device(self.device):
+            _check(self._lib.qless_tsqr_r_batched(self._plan, ctypes.c_void_p(self.work.data_ptr()),
+                                                  self.work_bytes, _stream(self.device)), "qless_tsqr_r_batched")
+        return self.Rs
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            self._lib.qless_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qless_tsqr_r_batched(Xs, **kw):
+    """R of every matrix of the list ``Xs`` in one persistent launch."""
+    plan = BatchPlan(Xs, **kw)
+    Rs = plan.run()
+    import torch
+    torch.cuda.current_stream(plan.device).synchronize()
+    plan.close()
+    return Rs
 
 
 # ------------------------------------------------------------------ timing

@@ -84,6 +84,8 @@ struct GramWork {
     double *A1 = nullptr, *A2 = nullptr, *A3 = nullptr, *A4 = nullptr;
     double* vec = nullptr;
     int* iw = nullptr;
+    void* tsqr_work = nullptr;   // workspace of the n x n TSQR of Z (SVQB R mode)
+    size_t tsqr_bytes = 0;
     size_t bytes = 0;
 };
 
@@ -105,6 +107,8 @@ GramWork gram_work_layout(const GramPlan& gp, int64_t n, void* base) {
     w.A4 = reinterpret_cast<double*>(take(sq));
     w.vec = reinterpret_cast<double*>(take((size_t)n * sizeof(double)));
     w.iw = reinterpret_cast<int*>(take(sizeof(int)));
+    w.tsqr_bytes = make_tsqr_plan(n, n, current_device_info().num_cus).work_bytes;
+    w.tsqr_work = take(w.tsqr_bytes);
     w.bytes = off;
     return w;
 }
@@ -209,8 +213,8 @@ int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_
     if (e == hipSuccess)
         e = launch_svqb_eig(gw.C, ni, trunc_tol, 0, U1, lam1, nullptr, nullptr, zdst, zld, gw.iw, stream);
     if (e == hipSuccess && out == QLESS_SVQB_R) {
-        TsqrPlan tp = make_tsqr_plan(n, n, d.num_cus);   // one wavefront, no tree
-        e = launch_tsqr(Zt, n, n, n, Z_or_R, ldz, nullptr, tp, stream);
+        TsqrPlan tp = make_tsqr_plan(n, n, d.num_cus);
+        e = launch_tsqr(Zt, n, n, n, Z_or_R, ldz, gw.tsqr_work, tp, stream);
     }
     if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
     return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
@@ -221,6 +225,25 @@ int qless_lstsq_finish(const double* Rt, int64_t n, int64_t ldr, double* x, doub
     if (Rt == nullptr || x == nullptr || n < 1 || ldr < n + 1) return QLESS_ERR_ARG;
     if (n + 1 > QLESS_MAX_N) return QLESS_ERR_UNSUPPORTED;
     return launch_lstsq(Rt, (int)n, ldr, x, resid, info, stream) == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int qless_batch_plan_create(const qless_matrix_desc* descs, int32_t count, int64_t tile_bytes, int32_t waves_per_cu,
+                            qless_batch_plan** plan) {
+    return batch_plan_create(descs, count, tile_bytes, waves_per_cu, plan);
+}
+
+void qless_batch_plan_destroy(qless_batch_plan* plan) { delete plan; }
+
+size_t qless_batch_plan_workspace_bytes(const qless_batch_plan* plan) { return batch_plan_bytes(plan); }
+
+int64_t qless_batch_plan_tiles(const qless_batch_plan* plan) { return batch_plan_tiles(plan); }
+
+int qless_batch_plan_upload(const qless_batch_plan* plan, void* work, size_t work_bytes, hipStream_t stream) {
+    return batch_plan_upload(plan, work, work_bytes, stream);
+}
+
+int qless_tsqr_r_batched(const qless_batch_plan* plan, void* work, size_t work_bytes, hipStream_t stream) {
+    return batch_run(plan, work, work_bytes, stream);
 }
 
 int qless_timing_enable(int on) {

@@ -250,6 +250,22 @@ hipError_t launch_lstsq(const double* Rt, int n, int64_t ldr, double* x, double*
 // Copy of a device int (used to publish an internal info word).
 hipError_t launch_copy_int(const int* src, int* dst, hipStream_t stream);
 
+// Device descriptor of one matrix of a batched call (built by the host plan).
+struct BatchMat {
+    const double* X;
+    double* R;
+    int64_t m, ldx, ldr, tile_rows, slot_base, cnt_base;
+    int n, np, accumulate, ntiles;
+};
+
+// Batched TSQR (batched.hip).
+int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_bytes, int waves_per_cu,
+                      qless_batch_plan** out);
+int batch_plan_upload(const qless_batch_plan* p, void* work, size_t work_bytes, hipStream_t s);
+int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStream_t s);
+size_t batch_plan_bytes(const qless_batch_plan* p);
+int64_t batch_plan_tiles(const qless_batch_plan* p);
+
 // Benchmark timing hooks (api.hip).
 void timing_begin(int which, hipStream_t stream);
 void timing_end(int which, hipStream_t stream);

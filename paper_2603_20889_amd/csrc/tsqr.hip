@@ -87,6 +87,9 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * 8;
     int64_t rpw = ceil_div(m > 0 ? m : 1, max_waves);
     rpw = ceil_div(rpw, panel) * panel;
+    // Small inputs (up to four panels) go to one wavefront: a tree launch
+    // would cost more than folding the few extra panels.
+    if (m <= 4 * panel) rpw = ceil_div(m > 0 ? m : 1, panel) * panel;
     p.rows_per_wave = rpw;
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
     p.fan_in = 16;
@@ -102,6 +105,7 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
 
 hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
                        void* work, const TsqrPlan& plan, hipStream_t stream) {
+    if (plan.levels > 0 && work == nullptr) return hipErrorInvalidValue;  // the tree needs its buffers
     double* ya = static_cast<double*>(work);
     double* yb = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
     const int ni = (int)n;

@@ -83,30 +83,16 @@ constexpr int waves_per_block() {
     return (NP * NP * 8 * 4 <= 65536) ? 4 : 2;
 }
 
-// One kernel for stage 1 and every tree level.
-//   X: rows [0, m) of a row-major matrix with leading dimension ldx, n columns.
-//   Wavefront w owns rows [w*rows_per_wave, min(m, (w+1)*rows_per_wave)).
-//   final == 0: write R_w (n x n, ld n) to Y + w*n*n.
-//   final != 0: (single wavefront) write sign-normalised R to Y with ld ldy.
+// Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
+// ldx) into the wavefront's R, panel by panel (layout for n <= 16).
 template <int NP, int RPL>
-__global__ void __launch_bounds__(64 * waves_per_block<NP>())
-tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int final_write, int buffer_ok) {
-    constexpr int WPB = waves_per_block<NP>();
-    __shared__ double Rsh[WPB][NP * NP];
-    const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int64_t w = (int64_t)blockIdx.x * WPB + wib;
-    if (w >= nwaves) return;
-    double* Rw = Rsh[wib];
-    for (int e = lane; e < NP * NP; e += kWave) Rw[e] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-
-    const int64_t r_begin = w * rows_per_wave;
-    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
-    for (int64_t base = r_begin; base < r_end; base += (int64_t)kWave * RPL) {
+__device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                             int64_t r_end, double* __restrict__ Rw, int lane) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    const bool buffer_ok = PANEL * ldx * 8 < 0x7FFFFFFF;
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
         double x[RPL][NP];
-        const bool full = base + (int64_t)kWave * RPL <= r_end;
+        const bool full = base + PANEL <= r_end;
         if (full && n == NP && buffer_ok) {
             // interior panel: buffer loads from a resource rebased at the panel,
             // lane offset in a VGPR, row-stripe offset in an SGPR.
@@ -141,17 +127,6 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
             }
         }
         FoldStep<NP, RPL, 0>::run(x, Rw, lane);
-    }
-
-    if (lane < n) {
-        const int r = lane;
-        double sgn = 1.0;
-        if (final_write && Rw[r * NP + r] < 0.0) sgn = -1.0;
-        double* out = final_write ? Y + (int64_t)r * ldy : Y + w * (int64_t)n * n + (int64_t)r * n;
-        for (int c = 0; c < n; ++c) {
-            double v = (c >= r) ? Rw[r * NP + c] : 0.0;
-            out[c] = final_write ? sgn * v + 0.0 : v;
-        }
     }
 }
 
@@ -232,25 +207,14 @@ struct FoldStep2D {
     }
 };
 
+// Same as fold_rows_1d for the column-group layout (n > 16).
 template <int NP, int RPL>
-__global__ void __launch_bounds__(64 * waves_per_block<NP>())
-tsqr_fold2d_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-                   int64_t nwaves, double* __restrict__ Y, int64_t ldy, int final_write, int buffer_ok) {
-    constexpr int WPB = waves_per_block<NP>();
+__device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                             int64_t r_end, double* __restrict__ Rw, int lane) {
     constexpr int NC = NP / kG2;
-    __shared__ double Rsh[WPB][NP * NP];
-    const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int64_t w = (int64_t)blockIdx.x * WPB + wib;
-    if (w >= nwaves) return;
-    double* Rw = Rsh[wib];
-    for (int e = lane; e < NP * NP; e += kWave) Rw[e] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    const int rg = lane / kG2, cg = lane % kG2;
-
-    const int64_t r_begin = w * rows_per_wave;
-    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
     constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
+    const bool buffer_ok = PANEL * ldx * 8 < 0x7FFFFFFF;
+    const int rg = lane / kG2, cg = lane % kG2;
     for (int64_t base = r_begin; base < r_end; base += PANEL) {
         double x[RPL][NC];
         const bool full = base + PANEL <= r_end;
@@ -279,17 +243,66 @@ tsqr_fold2d_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, 
         }
         FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
     }
+}
 
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_rows(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                          int64_t r_end, double* __restrict__ Rw, int lane) {
+    if constexpr (NP <= 16) fold_rows_1d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
+    else fold_rows_2d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
+}
+
+// Rows of a panel for an instance (the unit rows_per_wave is rounded to).
+template <int NP, int RPL>
+constexpr int64_t panel_rows() {
+    return (int64_t)(NP <= 16 ? kWave : kRG2) * RPL;
+}
+
+template <int NP>
+__device__ __forceinline__ void zero_r(double* __restrict__ Rw, int lane) {
+    for (int e = lane; e < NP * NP; e += kWave) Rw[e] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Write the wavefront's R (n x n, zeros below the diagonal) to out (ld).
+// With normalise, rows with a negative diagonal are negated and -0.0 is
+// written as +0.0.
+template <int NP>
+__device__ __forceinline__ void store_r(const double* __restrict__ Rw, int n, double* __restrict__ out, int64_t ld,
+                                        bool normalise, int lane) {
     if (lane < n) {
         const int r = lane;
-        double sgn = 1.0;
-        if (final_write && Rw[r * NP + r] < 0.0) sgn = -1.0;
-        double* out = final_write ? Y + (int64_t)r * ldy : Y + w * (int64_t)n * n + (int64_t)r * n;
+        const double sgn = (normalise && Rw[r * NP + r] < 0.0) ? -1.0 : 1.0;
+        double* o = out + (int64_t)r * ld;
         for (int c = 0; c < n; ++c) {
-            double v = (c >= r) ? Rw[r * NP + c] : 0.0;
-            out[c] = final_write ? sgn * v + 0.0 : v;
+            const double v = (c >= r) ? Rw[r * NP + c] : 0.0;
+            o[c] = normalise ? sgn * v + 0.0 : v;
         }
     }
+}
+
+// One kernel for stage 1 and every tree level.
+//   X: rows [0, m) of a row-major matrix with leading dimension ldx, n columns.
+//   Wavefront w owns rows [w*rows_per_wave, min(m, (w+1)*rows_per_wave)).
+//   final == 0: write R_w (n x n, ld n) to Y + w*n*n.
+//   final != 0: (single wavefront) write sign-normalised R to Y with ld ldy.
+template <int NP, int RPL>
+__global__ void __launch_bounds__(64 * waves_per_block<NP>())
+tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int final_write) {
+    constexpr int WPB = waves_per_block<NP>();
+    __shared__ double Rsh[WPB][NP * NP];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * WPB + wib;
+    if (w >= nwaves) return;
+    double* Rw = Rsh[wib];
+    zero_r<NP>(Rw, lane);
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
+    if (final_write) store_r<NP>(Rw, n, Y, ldy, true, lane);
+    else store_r<NP>(Rw, n, Y + w * (int64_t)n * n, n, false, lane);
 }
 
 template <int NP, int RPL>
@@ -297,15 +310,8 @@ hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t r
                        int64_t nwaves, double* Y, int64_t ldy, int final_write, hipStream_t stream) {
     constexpr int WPB = waves_per_block<NP>();
     const int64_t blocks = ceil_div(nwaves, WPB);
-    if constexpr (NP <= 16) {
-        hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream,
-                           X, m, n, ldx, rows_per_wave, nwaves, Y, ldy, final_write,
-                           (int)((int64_t)kWave * RPL * ldx * 8 < 0x7FFFFFFF));
-    } else {
-        hipLaunchKernelGGL((tsqr_fold2d_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream,
-                           X, m, n, ldx, rows_per_wave, nwaves, Y, ldy, final_write,
-                           (int)((int64_t)kRG2 * RPL * ldx * 8 < 0x7FFFFFFF));
-    }
+    hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream,
+                       X, m, n, ldx, rows_per_wave, nwaves, Y, ldy, final_write);
     return hipGetLastError();
 }
 

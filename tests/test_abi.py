@@ -89,3 +89,13 @@ def test_timing_read_rejects_unknown_kernel():
     ms = ctypes.c_double()
     cnt = ctypes.c_int64()
     assert q.load().qless_timing_read(b"nope", ctypes.byref(ms), ctypes.byref(cnt)) == q.QLESS_ERR_ARG
+
+
+def test_small_problems_plan_one_wavefront():
+    """An n x n (or few-panel) TSQR needs no tree, so no workspace beyond the
+    minimum -- the SVQB R mode relies on this for its n x n Z, and its own
+    workspace also reserves the TSQR slice."""
+    for n in (1, 8, 16, 24, 32, 48, 56, 64):
+        assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, n, n) == 256
+    assert (q.qless_workspace_bytes(q.QLESS_METHOD_SVQB, 10_000, 64)
+            >= q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2, 10_000, 64))
