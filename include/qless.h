@@ -133,6 +133,21 @@ int svqb(const double *X, int64_t m, int64_t n, int64_t ldx, int out,
 int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
                        double *resid, int32_t *info, hipStream_t stream);
 
+/* ------------------------------------------------------------ autotuning */
+
+/*
+ * Launch parameters of qless_tsqr_r for column count n, as chosen by an
+ * autotuner: waves_per_cu = stage-1 wavefronts per compute unit (row blocks
+ * k = CUs * waves_per_cu; 0 = default 8, at most 32), fan_in = blocks combined
+ * per tree wavefront (0 = default 16, 2..256), rows_per_lane = panel rows
+ * per lane, one of the compiled variants for that n (0 = default;
+ * QLESS_ERR_UNSUPPORTED if no such variant).  Process-wide, not thread-safe;
+ * query qless_workspace_bytes after changing it.  qless_tune_get returns the
+ * values in effect (defaults resolved).
+ */
+int qless_tune_set(int64_t n, int32_t waves_per_cu, int32_t fan_in, int32_t rows_per_lane);
+int qless_tune_get(int64_t n, int32_t *waves_per_cu, int32_t *fan_in, int32_t *rows_per_lane);
+
 /* ------------------------------------------------------------- batched */
 
 /*

@@ -37,7 +37,7 @@ EXPORTED = (
     "cholqr2_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
     "qless_timing_read", "qless_batch_plan_create", "qless_batch_plan_destroy",
     "qless_batch_plan_workspace_bytes", "qless_batch_plan_tiles", "qless_batch_plan_upload",
-    "qless_tsqr_r_batched",
+    "qless_tsqr_r_batched", "qless_tune_set", "qless_tune_get",
 )
 
 
@@ -94,6 +94,10 @@ def load() -> ctypes.CDLL:
     lib.qless_batch_plan_upload.restype = ctypes.c_int
     lib.qless_tsqr_r_batched.argtypes = [vp, vp, sz, vp]
     lib.qless_tsqr_r_batched.restype = ctypes.c_int
+    lib.qless_tune_set.argtypes = [i64, i32, i32, i32]
+    lib.qless_tune_set.restype = ctypes.c_int
+    lib.qless_tune_get.argtypes = [i64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qless_tune_get.restype = ctypes.c_int
     lib.qless_timing_enable.argtypes = [ctypes.c_int]
     lib.qless_timing_enable.restype = ctypes.c_int
     lib.qless_timing_reset.argtypes = []
@@ -308,6 +312,18 @@ def qless_tsqr_r_batched(Xs, **kw):
     torch.cuda.current_stream(plan.device).synchronize()
     plan.close()
     return Rs
+
+
+# ---------------------------------------------------------------- tuning
+
+def qless_tune_set(n: int, waves_per_cu: int = 0, fan_in: int = 0, rows_per_lane: int = 0) -> None:
+    _check(load().qless_tune_set(int(n), int(waves_per_cu), int(fan_in), int(rows_per_lane)), "qless_tune_set")
+
+
+def qless_tune_get(n: int) -> dict:
+    w, f, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().qless_tune_get(int(n), ctypes.byref(w), ctypes.byref(f), ctypes.byref(r)), "qless_tune_get")
+    return {"waves_per_cu": w.value, "fan_in": f.value, "rows_per_lane": r.value}
 
 
 # ------------------------------------------------------------------ timing

@@ -1,0 +1,161 @@
+"""Autotuner for the launch parameters of Q-less TSQR.
+
+For each column count n it times ``qless_tsqr_r`` on a synthetic m x n
+matrix over a small grid of
+  * rows_per_lane  -- panel height (the compiled variants for that n),
+  * waves_per_cu   -- stage-1 row blocks per compute unit,
+  * fan_in         -- triangles combined per tree wavefront,
+keeps the fastest, and stores the table in a JSON cache keyed by GPU
+architecture, library version and n.  ``apply_cached()`` loads the cache
+into the library (``qless_tune_set``); the environment variable
+QLESS_TUNE_FILE overrides the cache path and QLESS_TUNE=off disables it.
+For the batched form it picks the tile size and grid of a batch plan.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+
+import paper_2603_20889_amd as q
+
+WAVES_PER_CU = (4, 8, 12, 16)
+FAN_IN = (8, 16, 32)
+
+
+def cache_path() -> str:
+    env = os.environ.get("QLESS_TUNE_FILE")
+    if env:
+        return env
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "qless", "tsqr_tune.json")
+
+
+def _arch(device) -> str:
+    import torch
+    p = torch.cuda.get_device_properties(device)
+    return getattr(p, "gcnArchName", p.name)
+
+
+def _key(device) -> str:
+    return "%s|%s" % (_arch(device), q.version())
+
+
+def rows_per_lane_variants(n: int) -> list[int]:
+    """Compiled panel heights for n (the default first)."""
+    q.qless_tune_set(n, 0, 0, 0)
+    default = q.qless_tune_get(n)["rows_per_lane"]
+    out = [default]
+    for cand in (default // 2, default * 2):
+        if cand >= 1:
+            try:
+                q.qless_tune_set(n, 0, 0, cand)
+                out.append(cand)
+            except q.QlessError:
+                pass
+    q.qless_tune_set(n, 0, 0, 0)
+    return out
+
+
+def _time_tsqr(X, steps: int) -> float:
+    import torch
+    m, n = X.shape
+    R = torch.empty((n, n), dtype=torch.float64, device=X.device)
+    work, _ = q._workspace(q.QLESS_METHOD_TSQR, m, n, X.device)
+    for _ in range(2):
+        q.qless_tsqr_r(X, R=R, work=work)
+    torch.cuda.synchronize(X.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        q.qless_tsqr_r(X, R=R, work=work)
+    e1.record()
+    torch.cuda.synchronize(X.device)
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_tsqr(ns, device=None, target_bytes: float = 2e9, steps: int = 10, log=print) -> dict:
+    """Tune qless_tsqr_r for every n in ns on ~target_bytes matrices.
+    Returns {n: {"rows_per_lane", "waves_per_cu", "fan_in", "ms", "GBps"}}."""
+    import torch
+
+    import workloads as wl
+    device = device or torch.device("cuda:0")
+    table = {}
+    for n in ns:
+        m = max(1 << 16, int(target_bytes // (8 * n)))
+        X = wl.gaussian_torch(m, n, seed=1000 + n, device=device)
+        best = None
+        for rpl, wpc, fan in itertools.product(rows_per_lane_variants(n), WAVES_PER_CU, FAN_IN):
+            q.qless_tune_set(n, wpc, fan, rpl)
+            ms = _time_tsqr(X, steps)
+            if best is None or ms < best["ms"]:
+                best = {"rows_per_lane": rpl, "waves_per_cu": wpc, "fan_in": fan, "ms": ms,
+                        "GBps": 8.0 * m * n / (ms * 1e-3) / 1e9, "m": m}
+        q.qless_tune_set(n, best["waves_per_cu"], best["fan_in"], best["rows_per_lane"])
+        table[n] = best
+        log("[autotune] n=%d -> %s" % (n, json.dumps(best)))
+        del X
+        torch.cuda.empty_cache()
+    return table
+
+
+def tune_batched(Xs, device=None, tile_choices=(256 << 10, 1 << 20, 4 << 20, 16 << 20),
+                 wave_choices=(4, 8, 16), steps: int = 3, log=print) -> dict:
+    """Pick tile_bytes and waves_per_cu for a batch (list of GPU matrices)."""
+    import torch
+    best = None
+    for tb, wpc in itertools.product(tile_choices, wave_choices):
+        plan = q.BatchPlan(Xs, tile_bytes=tb, waves_per_cu=wpc)
+        plan.run()
+        torch.cuda.synchronize(device)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.run()
+        torch.cuda.synchronize(device)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        plan.close()
+        if best is None or ms < best["ms"]:
+            best = {"tile_bytes": tb, "waves_per_cu": wpc, "ms": ms}
+    log("[autotune] batched -> %s" % json.dumps(best))
+    return best
+
+
+def save(table: dict, device=None, path: str | None = None) -> str:
+    import torch
+    device = device or torch.device("cuda:0")
+    path = path or cache_path()
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        data = {}
+    data[_key(device)] = {str(n): v for n, v in table.items()}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return path
+
+
+def apply(table: dict) -> None:
+    for n, v in table.items():
+        q.qless_tune_set(int(n), int(v["waves_per_cu"]), int(v["fan_in"]), int(v["rows_per_lane"]))
+
+
+def apply_cached(device=None, path: str | None = None) -> dict | None:
+    """Load the cached table for this GPU and library version into the
+    library; returns it, or None when disabled or absent."""
+    if os.environ.get("QLESS_TUNE", "").lower() in ("0", "off", "no"):
+        return None
+    import torch
+    device = device or torch.device("cuda:0")
+    try:
+        data = json.load(open(path or cache_path()))
+    except (OSError, ValueError):
+        return None
+    table = data.get(_key(device))
+    if table:
+        apply(table)
+    return table

@@ -227,6 +227,14 @@ int qless_lstsq_finish(const double* Rt, int64_t n, int64_t ldr, double* x, doub
     return launch_lstsq(Rt, (int)n, ldr, x, resid, info, stream) == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 
+int qless_tune_set(int64_t n, int32_t waves_per_cu, int32_t fan_in, int32_t rows_per_lane) {
+    return tsqr_tune_set(n, waves_per_cu, fan_in, rows_per_lane);
+}
+
+int qless_tune_get(int64_t n, int32_t* waves_per_cu, int32_t* fan_in, int32_t* rows_per_lane) {
+    return tsqr_tune_get(n, waves_per_cu, fan_in, rows_per_lane);
+}
+
 int qless_batch_plan_create(const qless_matrix_desc* descs, int32_t count, int64_t tile_bytes, int32_t waves_per_cu,
                             qless_batch_plan** plan) {
     return batch_plan_create(descs, count, tile_bytes, waves_per_cu, plan);

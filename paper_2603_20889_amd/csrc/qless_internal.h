@@ -210,6 +210,10 @@ struct TsqrPlan {
 
 TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus);
 
+// Per-n launch-parameter overrides (0 = default); see qless_tune_set.
+int tsqr_tune_set(int64_t n, int waves_per_cu, int fan_in, int rows_per_lane);
+int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rows_per_lane);
+
 // Enqueue a full TSQR (stage 1 + tree + sign normalisation) into `work`.
 // Arguments have been validated by the caller.
 hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R,

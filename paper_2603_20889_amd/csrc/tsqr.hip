@@ -6,85 +6,102 @@
 
 namespace qless {
 
-hipError_t launch_fold_np1(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np2(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np3(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np5(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np6(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np7(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np8(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np10(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np12(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np14(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np16(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np24(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np32(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np40(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np48(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np56(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
-hipError_t launch_fold_np64(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
-                          int64_t ldy, int fin, hipStream_t s);
+// Kernel instances (tsqr_i*.hip): launch_fold_np<NP>_r<RPL>.
+#define QLESS_DECL(NP, RPL)                                                                              \
+    hipError_t launch_fold_np##NP##_r##RPL(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, \
+                                           int64_t nw, double* Y, int64_t ldy, int fin, hipStream_t s);
+#define QLESS_INSTANCES(X)                                                                          \
+    X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(10, 6) X(12, 5)          \
+    X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 9) X(64, 7)                      \
+    X(1, 32) X(2, 16) X(4, 8) X(8, 4) X(16, 2) X(32, 8) X(64, 4)
+QLESS_INSTANCES(QLESS_DECL)
+#undef QLESS_DECL
 
 namespace {
 
-// Padded column counts with a kernel instance, and their panel rows per lane.
+typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, int,
+                              hipStream_t);
+
 struct Instance {
     int npad;
     int rpl;
+    FoldFn fn;
 };
 
-Instance instance_for(int64_t n) {
+const Instance kInstances[] = {
+#define QLESS_ENTRY(NP, RPL) {NP, RPL, launch_fold_np##NP##_r##RPL},
+    QLESS_INSTANCES(QLESS_ENTRY)
+#undef QLESS_ENTRY
+};
+
+int npad_for(int64_t n) {
     static const int pads[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 24, 32, 40, 48, 56, 64};
-    int np = 64;
     for (int p : pads)
-        if (n <= p) { np = p; break; }
-    // n <= 16: RPL full rows per lane; n > 16: RPL rows of NP/8 columns per lane
-    int rpl = np <= 16 ? 64 / np : np == 64 ? 7 : 64 / (np / 8);
-    return {np, rpl};
+        if (n <= p) return p;
+    return 64;
 }
 
-hipError_t dispatch_fold(int np, const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                         double* Y, int64_t ldy, int fin, hipStream_t s) {
-    switch (np) {
-#define QLESS_CASE(NP, RPL) \
-    case NP: return launch_fold_np##NP(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
-        QLESS_CASE(1, 64) QLESS_CASE(2, 32) QLESS_CASE(3, 21) QLESS_CASE(4, 16)
-        QLESS_CASE(5, 12) QLESS_CASE(6, 10) QLESS_CASE(7, 9) QLESS_CASE(8, 8)
-        QLESS_CASE(10, 6) QLESS_CASE(12, 5) QLESS_CASE(14, 4) QLESS_CASE(16, 4)
-        QLESS_CASE(24, 21) QLESS_CASE(32, 16) QLESS_CASE(40, 12) QLESS_CASE(48, 10)
-        QLESS_CASE(56, 9) QLESS_CASE(64, 7)
-#undef QLESS_CASE
-        default: return hipErrorInvalidValue;
+// Default instance of a padded width: n <= 16 keeps RPL = 64/NP full rows per
+// lane (64 doubles); wider layouts keep about 64 doubles of RPL x NP/8.
+const Instance* find_instance(int np, int rpl) {
+    const Instance* def = nullptr;
+    for (const Instance& in : kInstances) {
+        if (in.npad != np) continue;
+        if (in.rpl == rpl) return &in;
+        if (!def) def = &in;   // the first listed instance of a width is its default
     }
+    return def;
+}
+
+// Launch-parameter overrides per column count (set by the autotuner).
+struct Tuning {
+    int waves_per_cu = 0, fan_in = 0, rpl = 0;
+};
+Tuning g_tuning[QLESS_MAX_N + 1];
+
+}  // namespace
+
+int tsqr_tune_set(int64_t n, int waves_per_cu, int fan_in, int rpl) {
+    if (n < 1 || n > QLESS_MAX_N || waves_per_cu < 0 || waves_per_cu > 32 || fan_in < 0 || fan_in == 1 ||
+        fan_in > 256 || rpl < 0)
+        return QLESS_ERR_ARG;
+    if (rpl != 0) {
+        const Instance* in = find_instance(npad_for(n), rpl);
+        if (!in || in->rpl != rpl) return QLESS_ERR_UNSUPPORTED;
+    }
+    g_tuning[n] = Tuning{waves_per_cu, fan_in, rpl};
+    return QLESS_OK;
+}
+
+int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rpl) {
+    if (n < 1 || n > QLESS_MAX_N) return QLESS_ERR_ARG;
+    const Tuning& t = g_tuning[n];
+    const Instance* in = find_instance(npad_for(n), t.rpl);
+    if (waves_per_cu) *waves_per_cu = t.waves_per_cu ? t.waves_per_cu : 8;
+    if (fan_in) *fan_in = t.fan_in ? t.fan_in : 16;
+    if (rpl) *rpl = in->rpl;
+    return QLESS_OK;
+}
+
+namespace {
+
+hipError_t dispatch_fold(const TsqrPlan& p, const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
+                         double* Y, int64_t ldy, int fin, hipStream_t s) {
+    const Instance* in = find_instance(p.npad, p.rows_per_lane);
+    if (!in) return hipErrorInvalidValue;
+    return in->fn(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
 
 }  // namespace
 
 TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     TsqrPlan p;
-    Instance in = instance_for(n);
-    p.npad = in.npad;
-    p.rows_per_lane = in.rpl;
-    const int64_t panel = (int64_t)(in.npad <= 16 ? kWave : tsqr_detail::kRG2) * in.rpl;
-    const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * 8;
+    const Tuning t = (n >= 1 && n <= QLESS_MAX_N) ? g_tuning[n] : Tuning{};
+    const Instance* in = find_instance(npad_for(n), t.rpl);
+    p.npad = in->npad;
+    p.rows_per_lane = in->rpl;
+    const int64_t panel = (int64_t)(in->npad <= 16 ? kWave : tsqr_detail::kRG2) * in->rpl;
+    const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * (t.waves_per_cu ? t.waves_per_cu : 8);
     int64_t rpw = ceil_div(m > 0 ? m : 1, max_waves);
     rpw = ceil_div(rpw, panel) * panel;
     // Small inputs (up to four panels) go to one wavefront: a tree launch
@@ -92,7 +109,7 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     if (m <= 4 * panel) rpw = ceil_div(m > 0 ? m : 1, panel) * panel;
     p.rows_per_wave = rpw;
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
-    p.fan_in = 16;
+    p.fan_in = t.fan_in ? t.fan_in : 16;
     int levels = 0;
     for (int64_t k = p.k0; k > 1; k = ceil_div(k, p.fan_in)) ++levels;
     p.levels = levels;
@@ -112,11 +129,11 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
     hipError_t e;
     timing_begin(kTimeTsqrStage1, stream);
     if (plan.levels == 0) {
-        e = dispatch_fold(plan.npad, X, m, ni, ldx, plan.rows_per_wave, 1, R, ldr, 1, stream);
+        e = dispatch_fold(plan, X, m, ni, ldx, plan.rows_per_wave, 1, R, ldr, 1, stream);
         timing_end(kTimeTsqrStage1, stream);
         return e;
     }
-    e = dispatch_fold(plan.npad, X, m, ni, ldx, plan.rows_per_wave, plan.k0, ya, n, 0, stream);
+    e = dispatch_fold(plan, X, m, ni, ldx, plan.rows_per_wave, plan.k0, ya, n, 0, stream);
     timing_end(kTimeTsqrStage1, stream);
     if (e != hipSuccess) return e;
     int64_t k = plan.k0;
@@ -126,7 +143,7 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
     for (int l = 0; l < plan.levels; ++l) {
         const int64_t kn = ceil_div(k, plan.fan_in);
         const bool last = (kn == 1);
-        e = dispatch_fold(plan.npad, src, k * n, ni, n, rpw, kn, last ? R : dst, last ? ldr : n,
+        e = dispatch_fold(plan, src, k * n, ni, n, rpw, kn, last ? R : dst, last ? ldr : n,
                           last ? 1 : 0, stream);
         if (e != hipSuccess) return e;
         k = kn;

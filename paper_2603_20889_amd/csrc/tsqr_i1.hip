@@ -3,19 +3,19 @@
 #include "tsqr_kernels.h"
 
 namespace qless {
-hipError_t launch_fold_np1(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np1_r64(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<1, 64>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np2(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np2_r32(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<2, 32>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np3(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np3_r21(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<3, 21>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np4_r16(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<4, 16>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }

@@ -3,19 +3,19 @@
 #include "tsqr_kernels.h"
 
 namespace qless {
-hipError_t launch_fold_np10(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np10_r6(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<10, 6>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np12(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np12_r5(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<12, 5>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np14(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np14_r4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<14, 4>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np16(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np16_r4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<16, 4>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }

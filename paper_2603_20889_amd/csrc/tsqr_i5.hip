@@ -3,11 +3,11 @@
 #include "tsqr_kernels.h"
 
 namespace qless {
-hipError_t launch_fold_np48(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np48_r10(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<48, 10>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }
-hipError_t launch_fold_np56(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np56_r9(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<56, 9>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }

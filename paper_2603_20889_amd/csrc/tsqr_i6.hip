@@ -3,7 +3,7 @@
 #include "tsqr_kernels.h"
 
 namespace qless {
-hipError_t launch_fold_np64(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
+hipError_t launch_fold_np64_r7(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw, double* Y,
                           int64_t ldy, int fin, hipStream_t s) {
     return tsqr_detail::launch_fold<64, 7>(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
 }

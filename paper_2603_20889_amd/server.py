@@ -1,0 +1,240 @@
+"""Continuous-batching server for least-squares requests via Q-less TSQR.
+
+A request carries [A b] (m x (n+1), FP64) and is answered with
+x = argmin ||A x - b||_2 and |rho| = ||A x - b||_2, read off R([A b]) =
+[[R_A, z], [0, rho]] (paper Sec. 1: least squares in a single pass over
+the data through the Q-less QR of the extended matrix).
+
+Serving loop (continuous batching, not a queue alone):
+  * requests wait in an admission queue until their HBM footprint
+    (8 m (n+1) bytes of data plus the (n+1)^2 running R) fits the budget and
+    an active slot is free;
+  * every step folds the next chunk of rows of EVERY active request into its
+    running R, all in one batched launch (``BatchPlan`` with accumulate), so
+    work of requests that arrived at different times overlaps on the device;
+    R([R_old; chunk]) = R([rows so far; chunk]) makes the n x n R the whole
+    per-request state, and it stays on the device;
+  * a request whose rows are exhausted gets its back substitution on the
+    device, its result is read back and its memory is released, which admits
+    the next waiting requests.
+
+The executor does the device work (``GpuExecutor``, through libqless); the
+scheduling logic only calls its admit / step / finish methods, so tests can
+drive it with a stand-in executor on the CPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Callable, Optional
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    arrival_s: float
+    m: int
+    n: int
+    seed: int
+    # filled in by the server
+    admit_s: float = math.nan
+    done_s: float = math.nan
+    rows_done: int = 0
+    x: object = None
+    resid: float = math.nan
+    info: int = 0
+    state: object = None      # executor-owned per-request state (data, running R)
+
+    @property
+    def footprint(self) -> int:
+        return 8 * self.m * (self.n + 1) + 8 * (self.n + 1) ** 2
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class GpuExecutor:
+    """Device executor: request data and running R live in HBM; each step is
+    one persistent batched launch over all active requests' chunks."""
+
+    def __init__(self, device, tile_bytes: int = 1 << 20, data_fn: Optional[Callable] = None):
+        import torch
+
+        import paper_2603_20889_amd as q
+        import workloads
+        self.q = q
+        self.torch = torch
+        self.device = device
+        self.tile_bytes = tile_bytes
+        self._data = data_fn or (lambda r: workloads.ls_request_data(r.m, r.n, r.seed, device=device)[0])
+        self.stream = torch.cuda.current_stream(device)
+        self.steps = 0
+
+    def admit(self, r: Request):
+        torch = self.torch
+        Ab = self._data(r)
+        R = torch.zeros((r.n + 1, r.n + 1), dtype=torch.float64, device=self.device)
+        r.state = {"Ab": Ab, "R": R}
+
+    def step(self, chunks):
+        Xs = [r.state["Ab"][lo:hi] for r, lo, hi in chunks]
+        Rs = [r.state["R"] for r, _, _ in chunks]
+        plan = self.q.BatchPlan(Xs, Rs=Rs, accumulate=[True] * len(chunks), tile_bytes=self.tile_bytes)
+        plan.run()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        plan.close()
+        self.steps += 1
+
+    def finish(self, r: Request):
+        x, res, info = self.q.qless_lstsq_finish(r.state["R"])
+        self.torch.cuda.current_stream(self.device).synchronize()
+        r.x = x.cpu().numpy()
+        r.resid = float(res.item())
+        r.info = int(info.item())
+        r.state = None
+
+
+class LstsqServer:
+    """Admission by HBM footprint, continuous batching of row chunks."""
+
+    def __init__(self, executor, hbm_budget_bytes: int, step_bytes: int = 1 << 30, max_active: int = 256,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = int(hbm_budget_bytes)
+        self.step_bytes = int(step_bytes)
+        self.max_active = int(max_active)
+        self.clock = clock
+        self.queue: collections.deque[Request] = collections.deque()
+        self.active: list[Request] = []
+        self.done: list[Request] = []
+        self.rejected: list[Request] = []
+        self.in_use = 0
+        self.max_queue = 0
+        self.max_active_seen = 0
+        self.t0 = 0.0
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def submit(self, r: Request):
+        if r.footprint > self.budget:        # can never fit: reject at once
+            self.rejected.append(r)
+            return
+        self.queue.append(r)
+        self.max_queue = max(self.max_queue, len(self.queue))
+
+    def _admit(self):
+        while self.queue and len(self.active) < self.max_active and self.in_use + self.queue[0].footprint <= self.budget:
+            r = self.queue.popleft()
+            self.ex.admit(r)
+            r.admit_s = self.now()
+            self.in_use += r.footprint
+            self.active.append(r)
+        self.max_active_seen = max(self.max_active_seen, len(self.active))
+
+    def _chunks(self):
+        """Next row range of every active request.  The step's byte budget is
+        shared evenly, with at least one 4096-row chunk per request."""
+        if not self.active:
+            return []
+        share = max(self.step_bytes // len(self.active), 1)
+        out = []
+        for r in self.active:
+            rows = max(4096, share // (8 * (r.n + 1)))
+            lo = r.rows_done
+            hi = min(r.m, lo + rows)
+            out.append((r, lo, hi))
+        return out
+
+    def step(self):
+        self._admit()
+        chunks = self._chunks()
+        if not chunks:
+            return False
+        self.ex.step(chunks)
+        still = []
+        for r, lo, hi in chunks:
+            r.rows_done = hi
+            if hi >= r.m:
+                self.ex.finish(r)
+                r.done_s = self.now()
+                self.in_use -= r.footprint
+                self.done.append(r)
+            else:
+                still.append(r)
+        self.active = still
+        return True
+
+    def run(self, requests, realtime: bool = True):
+        """Serve `requests` (sorted by arrival).  With realtime, arrivals are
+        released by the wall clock; otherwise all arrive at t = 0."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        self.t0 = self.clock()
+        while pending or self.queue or self.active:
+            t = self.now()
+            while pending and (not realtime or pending[0].arrival_s <= t):
+                self.submit(pending.popleft())
+            if not self.step():
+                if pending:
+                    wait = pending[0].arrival_s - self.now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
+                elif self.queue and not self.active:
+                    raise RuntimeError("request does not fit the HBM budget")
+        return self.stats()
+
+    def stats(self) -> dict:
+        lat = sorted(r.latency_s for r in self.done)
+        span = (max(r.done_s for r in self.done) - min(r.arrival_s for r in self.done)) if self.done else 0.0
+
+        def pct(p):
+            if not lat:
+                return math.nan
+            k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+            return lat[k]
+        return {"completed": len(self.done), "rejected": len(self.rejected),
+                "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "mean_ms": 1e3 * (sum(lat) / len(lat)) if lat else math.nan,
+                "solves_per_s": len(self.done) / span if span > 0 else math.nan,
+                "steps": getattr(self.ex, "steps", 0), "max_queue": self.max_queue,
+                "max_active": self.max_active_seen}
+
+
+class FifoServer:
+    """Baseline: one request per launch, in arrival order (no batching)."""
+
+    def __init__(self, executor, clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.clock = clock
+        self.done: list[Request] = []
+        self.t0 = 0.0
+
+    def run(self, requests, realtime: bool = True):
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        self.t0 = self.clock()
+        while pending:
+            r = pending.popleft()
+            now = self.clock() - self.t0
+            if realtime and r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            self.ex.admit(r)
+            r.admit_s = self.clock() - self.t0
+            self.ex.step([(r, 0, r.m)])
+            self.ex.finish(r)
+            r.done_s = self.clock() - self.t0
+            self.done.append(r)
+        lat = sorted(r.latency_s for r in self.done)
+        span = max(r.done_s for r in self.done) - min(r.arrival_s for r in self.done)
+        k50 = max(0, int(math.ceil(0.5 * len(lat))) - 1)
+        k99 = max(0, int(math.ceil(0.99 * len(lat))) - 1)
+        return {"completed": len(lat), "p50_ms": 1e3 * lat[k50], "p99_ms": 1e3 * lat[k99],
+                "mean_ms": 1e3 * sum(lat) / len(lat), "solves_per_s": len(lat) / span if span > 0 else math.nan}
+
+
+def make_requests(count: int, rate_per_s: float, seed: int = 5, mlo: float = 1e4, mhi: float = 5e7,
+                  nlo: int = 3, nhi: int = 47) -> list[Request]:
+    import workloads
+    return [Request(id=d["id"], arrival_s=d["arrival_s"], m=d["m"], n=d["n"], seed=d["seed"])
+            for d in workloads.server_requests(count, rate_per_s, seed, mlo, mhi, nlo, nhi)]
