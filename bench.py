@@ -97,6 +97,8 @@ def main() -> int:
     ap.add_argument("--m", type=int, default=50_000_000)
     ap.add_argument("--n", type=int, default=8)
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--ns", type=str, default="1,2,4,8,16,32,64",
+                    help="column counts of the m = 2^25 sweep")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) for HBM-counter calibration")
     args = ap.parse_args()
@@ -215,7 +217,7 @@ def main() -> int:
     if not args.no_sweep:
         sweep = []
         ms_s = 2 ** 25
-        for ns in (1, 2, 4, 8, 16, 32, 64):
+        for ns in [int(v) for v in args.ns.split(",") if v]:
             log("sweep m=2^25 n=%d" % ns)
             Xs, R0s = wl.config3(ns, 4, device=dev)
             Rs = torch.empty((ns, ns), dtype=torch.float64, device=dev)

@@ -39,7 +39,7 @@ constexpr int kBatchWpb = 2;  // wavefronts per workgroup of the batched kernel
 __device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <int NP, int RPL>
-__device__ void batch_tile(const BatchMat& M, int t, double* __restrict__ Rw, double* __restrict__ slots,
+__device__ __forceinline__ void batch_tile(const BatchMat& M, int t, double* __restrict__ Rw, double* __restrict__ slots,
                            int* __restrict__ counters, int lane) {
     using namespace tsqr_detail;
     const int n = M.n;
@@ -76,7 +76,7 @@ __device__ void batch_tile(const BatchMat& M, int t, double* __restrict__ Rw, do
 }
 
 // queue[0]: next tile, queue[1]: wavefronts finished (both reset by the last wavefront)
-__global__ void __launch_bounds__(64 * kBatchWpb)
+__global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
 batched_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles, int64_t ntiles, int64_t nwaves,
                double* __restrict__ slots, int* __restrict__ counters, int* __restrict__ queue, int np_max) {
     extern __shared__ double lds[];
@@ -84,7 +84,7 @@ batched_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles
     const int wib = threadIdx.x >> 6;
     const int64_t w = (int64_t)blockIdx.x * kBatchWpb + wib;
     if (w >= nwaves) return;
-    double* Rw = lds + (size_t)wib * np_max * np_max;
+    double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2);
     while (true) {
         int t = 0;
         if (lane == 0) t = __hip_atomic_fetch_add(queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -98,8 +98,8 @@ batched_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles
             case 4: batch_tile<4, 16>(M, tl.y, Rw, slots, counters, lane); break;
             case 8: batch_tile<8, 8>(M, tl.y, Rw, slots, counters, lane); break;
             case 16: batch_tile<16, 4>(M, tl.y, Rw, slots, counters, lane); break;
-            case 32: batch_tile<32, 16>(M, tl.y, Rw, slots, counters, lane); break;
-            default: batch_tile<64, 7>(M, tl.y, Rw, slots, counters, lane); break;
+            case 32: batch_tile<32, 12>(M, tl.y, Rw, slots, counters, lane); break;
+            default: batch_tile<64, 5>(M, tl.y, Rw, slots, counters, lane); break;
         }
     }
     // the last wavefront to leave resets the queue for the next launch
@@ -125,8 +125,8 @@ int64_t batch_panel_rows(int np) {
         case 4: return 64 * 16;
         case 8: return 64 * 8;
         case 16: return 64 * 4;
-        case 32: return 8 * 16;
-        default: return 8 * 7;
+        case 32: return 8 * 12;
+        default: return 8 * 5;
     }
 }
 
@@ -212,7 +212,7 @@ int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStrea
     char* b = static_cast<char*>(work);
     int* counters = reinterpret_cast<int*>(b + p->off_counters);
     int* queue = counters + (p->counter_ints - 2);
-    const size_t lds = (size_t)kBatchWpb * p->np_max * p->np_max * sizeof(double);
+    const size_t lds = (size_t)kBatchWpb * (p->np_max * (p->np_max + 1) / 2) * sizeof(double);
     const int64_t blocks = ceil_div(p->nwaves, kBatchWpb);
     hipLaunchKernelGGL(batched_kernel, dim3((unsigned)blocks), dim3(64 * kBatchWpb), lds, s,
                        reinterpret_cast<const BatchMat*>(b), reinterpret_cast<const int2*>(b + p->off_tiles),

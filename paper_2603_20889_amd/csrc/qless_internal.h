@@ -195,16 +195,16 @@ struct DeviceInfo {
 // on first use per device).
 const DeviceInfo& current_device_info();
 
-// Plan of a TSQR call: stage-1 wave count, rows per wave, tree levels.
+// Plan of a TSQR call: stage-1 wave count, rows per wave, tree shape.
 struct TsqrPlan {
     int npad = 0;              // padded column count of the kernel instance
     int rows_per_lane = 0;     // panel rows per lane (panel = 64 * rows_per_lane rows)
     int64_t rows_per_wave = 0; // stage-1 rows per wavefront
     int64_t k0 = 0;            // stage-1 wavefronts (= stacked R blocks)
     int fan_in = 0;            // blocks combined per tree wavefront
-    int levels = 0;            // tree launches after stage 1 (0: stage 1 finalises)
-    size_t ybytes_a = 0;       // bytes of the first ping-pong buffer
-    size_t ybytes_b = 0;       // bytes of the second ping-pong buffer
+    int levels = 0;            // tree levels (0: one wavefront writes R directly)
+    size_t counter_bytes = 0;  // group arrival counters of the tree
+    size_t slot_bytes = 0;     // stacked-triangle slots of every tree level
     size_t work_bytes = 0;     // total workspace
 };
 

@@ -2,6 +2,9 @@
 // wavefront count, rows per wavefront, tree levels, workspace) and the
 // stage-1 + tree launch sequence.  The kernels are in tsqr_kernels.h and are
 // instantiated per padded column count in tsqr_i*.hip.
+#include <atomic>
+#include <chrono>
+
 #include "tsqr_kernels.h"
 
 namespace qless {
@@ -9,18 +12,20 @@ namespace qless {
 // Kernel instances (tsqr_i*.hip): launch_fold_np<NP>_r<RPL>.
 #define QLESS_DECL(NP, RPL)                                                                              \
     hipError_t launch_fold_np##NP##_r##RPL(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, \
-                                           int64_t nw, double* Y, int64_t ldy, int fin, hipStream_t s);
+                                           int64_t nw, double* R, int64_t ldr, double* slots,           \
+                                           unsigned long long* counters, int fan_in,                    \
+                                           unsigned long long tag, hipStream_t s);
 #define QLESS_INSTANCES(X)                                                                          \
     X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(10, 6) X(12, 5)          \
-    X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 9) X(64, 7)                      \
+    X(14, 4) X(16, 4) X(24, 16) X(32, 12) X(40, 10) X(48, 8) X(56, 7) X(64, 5)                      \
     X(1, 32) X(2, 16) X(4, 8) X(8, 4) X(16, 2) X(32, 8) X(64, 4)
 QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
 
 namespace {
 
-typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, int,
-                              hipStream_t);
+typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, double*,
+                              unsigned long long*, int, unsigned long long, hipStream_t);
 
 struct Instance {
     int npad;
@@ -85,11 +90,17 @@ int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rpl) {
 
 namespace {
 
-hipError_t dispatch_fold(const TsqrPlan& p, const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                         double* Y, int64_t ldy, int fin, hipStream_t s) {
-    const Instance* in = find_instance(p.npad, p.rows_per_lane);
-    if (!in) return hipErrorInvalidValue;
-    return in->fn(X, m, n, ldx, rpw, nw, Y, ldy, fin, s);
+// Tags of successive calls (48 bits, never 0), starting from a value that
+// differs between processes, so that a workspace left over by an earlier
+// call or process never carries the current tag.
+unsigned long long next_call_tag() {
+    static std::atomic<unsigned long long> ctr{
+        (unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() * 0x9E3779B97F4A7C15ull};
+    unsigned long long t;
+    do {
+        t = ctr.fetch_add(1) & 0xFFFFFFFFFFFFull;
+    } while (t == 0);
+    return t;
 }
 
 }  // namespace
@@ -111,47 +122,31 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
     p.fan_in = t.fan_in ? t.fan_in : 16;
     int levels = 0;
-    for (int64_t k = p.k0; k > 1; k = ceil_div(k, p.fan_in)) ++levels;
+    int64_t slots = 0, counters = 0;
+    for (int64_t k = p.k0; k > 1; k = ceil_div(k, p.fan_in)) {
+        ++levels;
+        slots += k * n * n;
+        counters += ceil_div(k, p.fan_in);
+    }
     p.levels = levels;
-    const size_t blk = (size_t)n * (size_t)n * sizeof(double);
-    p.ybytes_a = align_up((size_t)p.k0 * blk, 256);
-    p.ybytes_b = align_up((size_t)ceil_div(p.k0, p.fan_in) * blk, 256);
-    p.work_bytes = levels == 0 ? 256 : p.ybytes_a + p.ybytes_b;
+    p.counter_bytes = align_up((size_t)counters * sizeof(unsigned long long), 256);
+    p.slot_bytes = align_up((size_t)slots * sizeof(double), 256);
+    p.work_bytes = levels == 0 ? 256 : p.counter_bytes + p.slot_bytes;
     return p;
 }
 
 hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
                        void* work, const TsqrPlan& plan, hipStream_t stream) {
     if (plan.levels > 0 && work == nullptr) return hipErrorInvalidValue;  // the tree needs its buffers
-    double* ya = static_cast<double*>(work);
-    double* yb = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
-    const int ni = (int)n;
-    hipError_t e;
+    const Instance* in = find_instance(plan.npad, plan.rows_per_lane);
+    if (!in) return hipErrorInvalidValue;
+    unsigned long long* counters = static_cast<unsigned long long*>(work);
+    double* slots = reinterpret_cast<double*>(static_cast<char*>(work) + plan.counter_bytes);
     timing_begin(kTimeTsqrStage1, stream);
-    if (plan.levels == 0) {
-        e = dispatch_fold(plan, X, m, ni, ldx, plan.rows_per_wave, 1, R, ldr, 1, stream);
-        timing_end(kTimeTsqrStage1, stream);
-        return e;
-    }
-    e = dispatch_fold(plan, X, m, ni, ldx, plan.rows_per_wave, plan.k0, ya, n, 0, stream);
+    const hipError_t e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, R, ldr, plan.levels ? slots : nullptr,
+                                plan.levels ? counters : nullptr, plan.fan_in, next_call_tag(), stream);
     timing_end(kTimeTsqrStage1, stream);
-    if (e != hipSuccess) return e;
-    int64_t k = plan.k0;
-    double* src = ya;
-    double* dst = yb;
-    const int64_t rpw = (int64_t)plan.fan_in * n;
-    for (int l = 0; l < plan.levels; ++l) {
-        const int64_t kn = ceil_div(k, plan.fan_in);
-        const bool last = (kn == 1);
-        e = dispatch_fold(plan, src, k * n, ni, n, rpw, kn, last ? R : dst, last ? ldr : n,
-                          last ? 1 : 0, stream);
-        if (e != hipSuccess) return e;
-        k = kn;
-        double* t = src;
-        src = dst;
-        dst = t;
-    }
-    return hipSuccess;
+    return e;
 }
 
 }  // namespace qless

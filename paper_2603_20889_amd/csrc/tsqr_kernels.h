@@ -31,15 +31,38 @@
 namespace qless {
 namespace tsqr_detail {
 
+// R is kept in LDS as a packed upper triangle: row J holds columns J..NP-1
+// starting at tri_row<NP>(J).
+template <int NP>
+__host__ __device__ constexpr int tri_row(int J) {
+    return J * NP - J * (J - 1) / 2;
+}
+
+template <int NP>
+constexpr int tri_size() {
+    return NP * (NP + 1) / 2;
+}
+
 
 // Fold one panel for NP <= 16: the column loop is a compile-time recursion so
 // that every register index is a constant.  Step J forms the K = NP - J
 // partial dot products of column J with columns J..NP-1 in each lane, sums
 // all K over the wavefront in one transposed butterfly, and applies the
 // reflector; the scalars (norm, beta, gamma) are wave-uniform.
+// Prefetch of the next panel into registers whose columns are finished:
+// after step J the pivot column J (and every earlier one) is dead, so the
+// next panel's columns are loaded into them while the later steps run.
+struct PanelPrefetch {
+    bool on;                       // wave-uniform: the next panel is a full interior panel
+    __amdgpu_buffer_rsrc_t rs;     // resource rebased at the next panel
+    int vo;                        // lane offset (bytes)
+    int so;                        // row-stripe offset (bytes)
+};
+
 template <int NP, int RPL, int J>
 struct FoldStep {
-    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, int lane) {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, int lane,
+                                               const PanelPrefetch& pf) {
         if constexpr (J < NP) {
             constexpr int K = NP - J;
             double p[K], tot[K], rj[K];
@@ -51,7 +74,7 @@ struct FoldStep {
                 p[t] = s;
             }
 #pragma unroll
-            for (int t = 0; t < K; ++t) rj[t] = Rw[J * NP + J + t];
+            for (int t = 0; t < K; ++t) rj[t] = Rw[tri_row<NP>(J) + t];
             wave_sum_multi<K>(p, tot, lane);
             const double alpha = rj[0];
             const double s = tot[0];
@@ -70,63 +93,102 @@ struct FoldStep {
                 rj[0] = beta;
                 if (lane == 0) {
 #pragma unroll
-                    for (int t = 0; t < K; ++t) Rw[J * NP + J + t] = rj[t];
+                    for (int t = 0; t < K; ++t) Rw[tri_row<NP>(J) + t] = rj[t];
                 }
             }
-            FoldStep<NP, RPL, J + 1>::run(x, Rw, lane);
+            if constexpr (J % 2 == 1) {
+                if (pf.on) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) {
+                        const f64x2 v = __builtin_bit_cast(
+                            f64x2, __builtin_amdgcn_raw_buffer_load_b128(pf.rs, pf.vo + (J - 1) * 8, pf.so * i, 0));
+                        x[i][J - 1] = v[0];
+                        x[i][J] = v[1];
+                    }
+                }
+            } else if constexpr (J == NP - 1) {
+                if (pf.on) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i)
+                        x[i][J] = __builtin_bit_cast(
+                            double, __builtin_amdgcn_raw_buffer_load_b64(pf.rs, pf.vo + J * 8, pf.so * i, 0));
+                }
+            }
+            FoldStep<NP, RPL, J + 1>::run(x, Rw, lane, pf);
         }
     }
 };
 
 template <int NP>
 constexpr int waves_per_block() {
-    return (NP * NP * 8 * 4 <= 65536) ? 4 : 2;
+    return (tri_size<NP>() * 8 * 4 <= 65536) ? 4 : 2;
 }
 
 // Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
 // ldx) into the wavefront's R, panel by panel (layout for n <= 16).
 template <int NP, int RPL>
+__device__ __forceinline__ void load_panel_1d(double (&x)[RPL][NP], const double* __restrict__ X, int n, int64_t ldx,
+                                              int64_t base, int64_t r_end, bool fast, int lane) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    if (fast && base + PANEL <= r_end) {
+        // interior panel: buffer loads from a resource rebased at the panel,
+        // lane offset in a VGPR, row-stripe offset in an SGPR.
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+        const int vo = lane * (int)(ldx * 8);
+        const int so = (int)(ldx * 8 * kWave);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+#pragma unroll
+            for (int c = 0; c < NP; c += 2) {
+                if (c + 1 < NP) {
+                    const f64x2 v =
+                        __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + c * 8, so * i, 0));
+                    x[i][c] = v[0];
+                    x[i][c + 1] = v[1];
+                } else {
+                    x[i][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + c * 8, so * i, 0));
+                }
+            }
+        }
+    } else {
+        // tail panel or padded width: guarded loads, zero fill
+        const int64_t left = r_end - base - lane;   // rows of this lane's stripe still in range
+        const double* x0 = X + (left > 0 ? base + lane : 0) * ldx;
+        const int64_t step = (int64_t)kWave * ldx;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const bool ok = (int64_t)kWave * i < left;
+#pragma unroll
+            for (int c = 0; c < NP; ++c) x[i][c] = (ok && c < n) ? x0[step * i + c] : 0.0;
+        }
+    }
+}
+
+// Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
+// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  While a
+// panel is folded, the next one (when it is a full interior panel) streams
+// into the registers of the columns already finished.
+template <int NP, int RPL>
 __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
                                              int64_t r_end, double* __restrict__ Rw, int lane) {
     constexpr int64_t PANEL = (int64_t)kWave * RPL;
-    const bool buffer_ok = PANEL * ldx * 8 < 0x7FFFFFFF;
-    for (int64_t base = r_begin; base < r_end; base += PANEL) {
-        double x[RPL][NP];
-        const bool full = base + PANEL <= r_end;
-        if (full && n == NP && buffer_ok) {
-            // interior panel: buffer loads from a resource rebased at the panel,
-            // lane offset in a VGPR, row-stripe offset in an SGPR.
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
-            const int vo = lane * (int)(ldx * 8);
-            const int so = (int)(ldx * 8 * kWave);
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-#pragma unroll
-                for (int c = 0; c < NP; c += 2) {
-                    if (c + 1 < NP) {
-                        const f64x2 v = __builtin_bit_cast(
-                            f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + c * 8, so * i, 0));
-                        x[i][c] = v[0];
-                        x[i][c + 1] = v[1];
-                    } else {
-                        x[i][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + c * 8, so * i, 0));
-                    }
-                }
-            }
-        } else {
-            // tail panel or padded width: guarded loads, zero fill
-            const int64_t left = r_end - base - lane;   // rows of this lane's stripe still in range
-            const double* x0 = X + (left > 0 ? base + lane : 0) * ldx;
-            const int64_t step = (int64_t)kWave * ldx;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const bool ok = (int64_t)kWave * i < left;
-#pragma unroll
-                for (int c = 0; c < NP; ++c) x[i][c] = (ok && c < n) ? x0[step * i + c] : 0.0;
-            }
-        }
-        FoldStep<NP, RPL, 0>::run(x, Rw, lane);
+    if (r_begin >= r_end) return;
+    const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
+    double x[RPL][NP];
+    load_panel_1d<NP, RPL>(x, X, n, ldx, r_begin, r_end, fast, lane);
+    for (int64_t base = r_begin;;) {
+        const int64_t next = base + PANEL;
+        PanelPrefetch pf;
+        pf.on = fast && next + PANEL <= r_end;
+        pf.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + (pf.on ? next : 0) * ldx), (short)0,
+                                                  0x7FFFFFFF, 0x00020000);
+        pf.vo = lane * (int)(ldx * 8);
+        pf.so = (int)(ldx * 8 * kWave);
+        FoldStep<NP, RPL, 0>::run(x, Rw, lane, pf);
+        if (next >= r_end) break;
+        if (!pf.on) load_panel_1d<NP, RPL>(x, X, n, ldx, next, r_end, false, lane);
+        base = next;
     }
 }
 
@@ -163,7 +225,8 @@ __device__ __forceinline__ double sum_over_row_groups(double v) {
 template <int NP, int RPL, int J>
 struct FoldStep2D {
     static constexpr int NC = NP / kG2;
-    __device__ static __forceinline__ void run(double (&x)[RPL][NP / kG2], double* __restrict__ Rw, int lane) {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP / kG2], double* __restrict__ Rw, int lane,
+                                               const PanelPrefetch& pf) {
         if constexpr (J < NP) {
             constexpr int cgJ = J % kG2;
             constexpr int uJ = J / kG2;
@@ -179,12 +242,13 @@ struct FoldStep2D {
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) t = fma(piv[i], x[i][uJ + a], t);
                 p[a] = t;
-                r[a] = Rw[J * NP + cg + kG2 * (uJ + a)];
+                const int c = cg + kG2 * (uJ + a);           // c < J only in finished slots: clamp
+                r[a] = Rw[tri_row<NP>(J) + (c > J ? c - J : 0)];
             }
 #pragma unroll
             for (int a = 0; a < A; ++a) p[a] = sum_over_row_groups(p[a]);
             const double s = readlane_f64(p[0], cgJ);   // |panel part of column J|^2
-            const double alpha = Rw[J * NP + J];
+            const double alpha = Rw[tri_row<NP>(J)];
             if (s != 0.0) {
                 const double nrm = sqrt(fma(alpha, alpha, s));
                 const double beta = (alpha >= 0.0) ? -nrm : nrm;
@@ -198,14 +262,53 @@ struct FoldStep2D {
                     coef = live ? coef : 0.0;
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) x[i][uJ + a] = fma(-coef, piv[i], x[i][uJ + a]);
-                    if (live && lane < kG2) Rw[J * NP + c] = fma(-coef, u0, r[a]);
+                    if (live && lane < kG2) Rw[tri_row<NP>(J) + c - J] = fma(-coef, u0, r[a]);
                 }
-                if (lane == 0) Rw[J * NP + J] = beta;
+                if (lane == 0) Rw[tri_row<NP>(J)] = beta;
             }
-            FoldStep2D<NP, RPL, J + 1>::run(x, Rw, lane);
+            if constexpr (J % kG2 == kG2 - 1) {   // slot uJ holds only finished columns now
+                if (pf.on) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i)
+                        x[i][uJ] = __builtin_bit_cast(
+                            double, __builtin_amdgcn_raw_buffer_load_b64(pf.rs, pf.vo, pf.so * i + kG2 * uJ * 8, 0));
+                }
+            }
+            FoldStep2D<NP, RPL, J + 1>::run(x, Rw, lane, pf);
         }
     }
 };
+
+template <int NP, int RPL>
+__device__ __forceinline__ void load_panel_2d(double (&x)[RPL][NP / kG2], const double* __restrict__ X, int n,
+                                              int64_t ldx, int64_t base, int64_t r_end, bool fast, int lane) {
+    constexpr int NC = NP / kG2;
+    constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
+    const int rg = lane / kG2, cg = lane % kG2;
+    if (fast && base + PANEL <= r_end) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+        const int vo = (int)((rg * ldx + cg) * 8);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+#pragma unroll
+            for (int u = 0; u < NC; ++u)
+                x[i][u] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, (int)((kRG2 * i * ldx + kG2 * u) * 8), 0));
+    } else {
+        const int64_t left = r_end - base - rg;
+        const double* x0 = X + (left > 0 ? base + rg : 0) * ldx;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const bool ok = (int64_t)kRG2 * i < left;
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int c = cg + kG2 * u;
+                x[i][u] = (ok && c < n) ? x0[(int64_t)kRG2 * i * ldx + c] : 0.0;
+            }
+        }
+    }
+}
 
 // Same as fold_rows_1d for the column-group layout (n > 16).
 template <int NP, int RPL>
@@ -213,35 +316,23 @@ __device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n
                                              int64_t r_end, double* __restrict__ Rw, int lane) {
     constexpr int NC = NP / kG2;
     constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
-    const bool buffer_ok = PANEL * ldx * 8 < 0x7FFFFFFF;
+    if (r_begin >= r_end) return;
+    const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
     const int rg = lane / kG2, cg = lane % kG2;
-    for (int64_t base = r_begin; base < r_end; base += PANEL) {
-        double x[RPL][NC];
-        const bool full = base + PANEL <= r_end;
-        if (full && n == NP && buffer_ok) {
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
-            const int vo = (int)((rg * ldx + cg) * 8);
-#pragma unroll
-            for (int i = 0; i < RPL; ++i)
-#pragma unroll
-                for (int u = 0; u < NC; ++u)
-                    x[i][u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                             rs, vo, (int)((kRG2 * i * ldx + kG2 * u) * 8), 0));
-        } else {
-            const int64_t left = r_end - base - rg;
-            const double* x0 = X + (left > 0 ? base + rg : 0) * ldx;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const bool ok = (int64_t)kRG2 * i < left;
-#pragma unroll
-                for (int u = 0; u < NC; ++u) {
-                    const int c = cg + kG2 * u;
-                    x[i][u] = (ok && c < n) ? x0[(int64_t)kRG2 * i * ldx + c] : 0.0;
-                }
-            }
-        }
-        FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
+    double x[RPL][NC];
+    load_panel_2d<NP, RPL>(x, X, n, ldx, r_begin, r_end, fast, lane);
+    for (int64_t base = r_begin;;) {
+        const int64_t next = base + PANEL;
+        PanelPrefetch pf;
+        pf.on = fast && next + PANEL <= r_end;
+        pf.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + (pf.on ? next : 0) * ldx), (short)0,
+                                                  0x7FFFFFFF, 0x00020000);
+        pf.vo = (int)((rg * ldx + cg) * 8);
+        pf.so = (int)(kRG2 * ldx * 8);
+        FoldStep2D<NP, RPL, 0>::run(x, Rw, lane, pf);
+        if (next >= r_end) break;
+        if (!pf.on) load_panel_2d<NP, RPL>(x, X, n, ldx, next, r_end, false, lane);
+        base = next;
     }
 }
 
@@ -260,7 +351,7 @@ constexpr int64_t panel_rows() {
 
 template <int NP>
 __device__ __forceinline__ void zero_r(double* __restrict__ Rw, int lane) {
-    for (int e = lane; e < NP * NP; e += kWave) Rw[e] = 0.0;
+    for (int e = lane; e < tri_size<NP>(); e += kWave) Rw[e] = 0.0;
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -272,26 +363,52 @@ __device__ __forceinline__ void store_r(const double* __restrict__ Rw, int n, do
                                         bool normalise, int lane) {
     if (lane < n) {
         const int r = lane;
-        const double sgn = (normalise && Rw[r * NP + r] < 0.0) ? -1.0 : 1.0;
+        const double sgn = (normalise && Rw[tri_row<NP>(r)] < 0.0) ? -1.0 : 1.0;
         double* o = out + (int64_t)r * ld;
         for (int c = 0; c < n; ++c) {
-            const double v = (c >= r) ? Rw[r * NP + c] : 0.0;
+            const double v = (c >= r) ? Rw[tri_row<NP>(r) + c - r] : 0.0;
             o[c] = normalise ? sgn * v + 0.0 : v;
         }
     }
 }
 
-// One kernel for stage 1 and every tree level.
-//   X: rows [0, m) of a row-major matrix with leading dimension ldx, n columns.
-//   Wavefront w owns rows [w*rows_per_wave, min(m, (w+1)*rows_per_wave)).
-//   final == 0: write R_w (n x n, ld n) to Y + w*n*n.
-//   final != 0: (single wavefront) write sign-normalised R to Y with ld ldy.
+// Arrival at a tree group of `gsize` blocks.  The counter word holds
+// (tag << 16) | arrivals, where tag identifies the call: the first arriver
+// of a call finds a different tag (a previous call's, or an uninitialised
+// word) and restarts the count at 1, so the workspace needs no zeroing; the
+// last arriver clears the word, so a replay with the same tag (a captured
+// graph) also starts from zero.  Returns true in every lane of the
+// wavefront that completed the group.
+__device__ __forceinline__ bool tree_arrive(unsigned long long* word, unsigned long long tag, int gsize, int lane) {
+    int last = 0;
+    if (lane == 0) {
+        unsigned long long old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long nw;
+        while (true) {
+            nw = ((old >> 16) == tag) ? old + 1ull : ((tag << 16) | 1ull);
+            if (__hip_atomic_compare_exchange_strong(word, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+        last = ((nw & 0xFFFFull) == (unsigned long long)gsize) ? 1 : 0;
+        if (last) __hip_atomic_store(word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return __builtin_amdgcn_readfirstlane(last) != 0;
+}
+
+// The whole Q-less TSQR of one matrix in one launch (Alg. 2).
+//   Stage 1: wavefront w folds rows [w*rows_per_wave, ...) of X into R_w.
+//   Stage 2: R_w goes to its level-0 slot; the wavefront that completes a
+//   group of fan_in siblings folds the group's stacked triangles into the
+//   next level, and so on; the one completing the root writes R (ld ldr,
+//   non-negative diagonal).  No wavefront waits for another.
 template <int NP, int RPL>
-__global__ void __launch_bounds__(64 * waves_per_block<NP>())
-tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int final_write) {
+__global__ void __launch_bounds__(64 * waves_per_block<NP>()) __attribute__((amdgpu_waves_per_eu(2)))
+tsqr_fused_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                  int64_t nwaves, double* __restrict__ R, int64_t ldr, double* __restrict__ slots,
+                  unsigned long long* __restrict__ counters, int fan_in, unsigned long long tag) {
     constexpr int WPB = waves_per_block<NP>();
-    __shared__ double Rsh[WPB][NP * NP];
+    __shared__ double Rsh[WPB][tri_size<NP>()];
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
     const int64_t w = (int64_t)blockIdx.x * WPB + wib;
@@ -301,17 +418,33 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
     fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
-    if (final_write) store_r<NP>(Rw, n, Y, ldy, true, lane);
-    else store_r<NP>(Rw, n, Y + w * (int64_t)n * n, n, false, lane);
+    const int64_t nn = (int64_t)n * n;
+    int64_t count = nwaves, idx = w, sbase = 0, cbase = 0;
+    while (count > 1) {
+        store_r<NP>(Rw, n, slots + sbase + idx * nn, n, false, lane);
+        __threadfence();
+        const int64_t g = idx / fan_in;
+        const int gsize = (int)((count - g * fan_in < fan_in) ? count - g * fan_in : fan_in);
+        if (!tree_arrive(counters + cbase + g, tag, gsize, lane)) return;
+        __threadfence();
+        zero_r<NP>(Rw, lane);
+        fold_rows<NP, RPL>(slots + sbase + g * fan_in * nn, n, n, 0, (int64_t)gsize * n, Rw, lane);
+        sbase += count * nn;
+        cbase += ceil_div(count, fan_in);
+        idx = g;
+        count = ceil_div(count, fan_in);
+    }
+    store_r<NP>(Rw, n, R, ldr, true, lane);
 }
 
 template <int NP, int RPL>
-hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-                       int64_t nwaves, double* Y, int64_t ldy, int final_write, hipStream_t stream) {
+hipError_t launch_fused(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave, int64_t nwaves,
+                        double* R, int64_t ldr, double* slots, unsigned long long* counters, int fan_in,
+                        unsigned long long tag, hipStream_t stream) {
     constexpr int WPB = waves_per_block<NP>();
     const int64_t blocks = ceil_div(nwaves, WPB);
-    hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream,
-                       X, m, n, ldx, rows_per_wave, nwaves, Y, ldy, final_write);
+    hipLaunchKernelGGL((tsqr_fused_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, X, m, n,
+                       ldx, rows_per_wave, nwaves, R, ldr, slots, counters, fan_in, tag);
     return hipGetLastError();
 }
 

@@ -1,0 +1,56 @@
+"""Launch-parameter table of qless_tsqr_r (host side; no GPU needed)."""
+import json
+
+import pytest
+
+import paper_2603_20889_amd as q
+from paper_2603_20889_amd import autotune
+
+
+@pytest.fixture(autouse=True)
+def reset_tuning():
+    yield
+    for n in range(1, 65):
+        q.qless_tune_set(n, 0, 0, 0)
+
+
+def test_defaults_and_round_trip():
+    d = q.qless_tune_get(8)
+    assert d == {"waves_per_cu": 8, "fan_in": 16, "rows_per_lane": 8}
+    q.qless_tune_set(8, 12, 32, 4)
+    assert q.qless_tune_get(8) == {"waves_per_cu": 12, "fan_in": 32, "rows_per_lane": 4}
+
+
+def test_invalid_and_unsupported_values():
+    with pytest.raises(q.QlessError):
+        q.qless_tune_set(0, 8, 16, 0)
+    with pytest.raises(q.QlessError):
+        q.qless_tune_set(8, 64, 16, 0)
+    with pytest.raises(q.QlessError):
+        q.qless_tune_set(8, 8, 1, 0)
+    with pytest.raises(q.QlessError) as e:
+        q.qless_tune_set(8, 8, 16, 3)          # no compiled 3-rows-per-lane variant for n = 8
+    assert e.value.status == q.QLESS_ERR_UNSUPPORTED
+
+
+def test_tuning_changes_the_plan():
+    base = q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 50_000_000, 8)
+    q.qless_tune_set(8, 16, 0, 0)     # twice the stage-1 blocks -> more stacked triangles
+    assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 50_000_000, 8) > base
+
+
+def test_variants_listed():
+    assert autotune.rows_per_lane_variants(8) == [8, 4]
+    assert autotune.rows_per_lane_variants(16)[0] == 4
+
+
+def test_apply_and_cache_file(tmp_path, monkeypatch):
+    table = {"8": {"rows_per_lane": 4, "waves_per_cu": 12, "fan_in": 8, "ms": 1.0}}
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"fakegpu|v": table}))
+    monkeypatch.setattr(autotune, "_key", lambda device: "fakegpu|v")
+    got = autotune.apply_cached(device="x", path=str(path))
+    assert got == table
+    assert q.qless_tune_get(8) == {"waves_per_cu": 12, "fan_in": 8, "rows_per_lane": 4}
+    monkeypatch.setenv("QLESS_TUNE", "off")
+    assert autotune.apply_cached(device="x", path=str(path)) is None
