@@ -99,6 +99,9 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--ns", type=str, default="1,2,4,8,16,32,64",
                     help="column counts of the m = 2^25 sweep")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=300)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) for HBM-counter calibration")
     args = ap.parse_args()
@@ -169,6 +172,7 @@ def main() -> int:
                      "kernel": "tsqr_stage1", "kernel_ms": round(st_avg, 5),
                      "algorithmic_bytes_per_launch": nbytes},
         "accuracy": {"e_R_vs_R0": e_r},
+        "kernel_hash": kernel_source_hash(),
         "pct_hbm_peak_step": round(100.0 * value / HBM_PEAK_GBS, 2),
     }
 
@@ -203,10 +207,12 @@ def main() -> int:
         out["compare"] = comp
 
     if args.calib_copy:
+        # a plain streaming kernel of known traffic for HBM-counter calibration:
+        # torch.neg reads 1 GiB and writes 1 GiB (kernel name contains "neg")
         src = torch.empty(2 ** 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = src.numel() * 8
         del src, dst
@@ -215,47 +221,151 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     if not args.no_sweep:
-        sweep = []
-        ms_s = 2 ** 25
-        for ns in [int(v) for v in args.ns.split(",") if v]:
-            log("sweep m=2^25 n=%d" % ns)
-            Xs, R0s = wl.config3(ns, 4, device=dev)
-            Rs = torch.empty((ns, ns), dtype=torch.float64, device=dev)
-            ws, _ = q._workspace(q.QLESS_METHOD_TSQR, ms_s, ns, dev)
-            steps = 20 if ns <= 16 else 5
-            flush = torch.empty(2 ** 27, dtype=torch.float64, device=dev) if ns <= 4 else None
+        out["sweep"] = bench_sweep(q, wl, dev, log, [int(v) for v in args.ns.split(",") if v])
 
-            def f():
-                if flush is not None:      # evict the MALL between calls: 1 GiB write
-                    flush.zero_()
-                q.qless_tsqr_r(Xs, R=Rs, work=ws)
-
-            q.timing_reset()
-            q.timing_enable(True)
-            t_ms, _ = time_calls(f, steps, 2)
-            q.timing_enable(False)
-            k_ms, k_cnt = q.timing_read("tsqr_stage1")
-            q.timing_reset()
-            k_avg = k_ms / max(k_cnt, 1)
-            if flush is not None:
-                t_ms = None  # the step time includes the flush; report the kernel time only
-            er = float(np.linalg.norm(Rs.cpu().numpy() - R0s) / np.linalg.norm(R0s))
-            rec = {"n": ns, "stage1_ms": round(k_avg, 5),
-                   "stage1_GBps": round(tsqr_bytes(ms_s, ns) / (k_avg * 1e-3) / 1e9, 1),
-                   "stage1_frac_hbm": round(tsqr_bytes(ms_s, ns) / (k_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                   "stage1_TFps": round(tsqr_flops(ms_s, ns) / (k_avg * 1e-3) / 1e12, 2),
-                   "e_R": er}
-            if t_ms is not None:
-                rec["step_ms"] = round(t_ms, 5)
-                rec["step_GBps"] = round(tsqr_bytes(ms_s, ns) / (t_ms * 1e-3) / 1e9, 1)
-            sweep.append(rec)
-            log(json.dumps(rec))
-            del Xs, ws, flush
-            torch.cuda.empty_cache()
-        out["sweep"] = sweep
+    if not args.no_batched:
+        out["batched"] = bench_batched(q, wl, dev, log)
+    if not args.no_served:
+        out["served"] = bench_served(q, dev, log, args.served_requests)
 
     print(json.dumps(out), flush=True)
     return 0
+
+
+def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25):
+    """Column sweep m = 2^25, n in ns, sigma log-spaced to 10^-k, k in {0, 4, 8}:
+    accuracy of TSQR and CholQR2 for every (n, k); timing (k = 4) of the
+    TSQR launch (HIP events around it) and of the whole CholQR2 call."""
+    import numpy as np
+    import torch
+    sweep = []
+    for ns in ns:
+        rec = {"n": ns, "m": m}
+        for k in (0, 4, 8):
+            log("sweep m=2^25 n=%d k=%d" % (ns, k))
+            Xs, R0s = wl.config3(ns, k, m=m, device=dev)
+            Rs = torch.empty((ns, ns), dtype=torch.float64, device=dev)
+            ws, _ = q._workspace(q.QLESS_METHOD_TSQR, m, ns, dev)
+            q.qless_tsqr_r(Xs, R=Rs, work=ws)
+            Rc, info = q.cholqr2_r(Xs)
+            torch.cuda.synchronize()
+            nR0 = np.linalg.norm(R0s)
+            rec["tsqr_e_R_k%d" % k] = float(np.linalg.norm(Rs.cpu().numpy() - R0s) / nR0)
+            rec["cholqr2_e_R_k%d" % k] = float(np.linalg.norm(Rc.cpu().numpy() - R0s) / nR0)
+            rec["cholqr2_info_k%d" % k] = int(info.item())
+            if k == 4:
+                steps = 20 if ns <= 16 else 5
+                flush = torch.empty(2 ** 27, dtype=torch.float64, device=dev) if ns <= 4 else None
+
+                def f():
+                    if flush is not None:      # evict the 256 MB MALL between calls: 1 GiB write
+                        flush.zero_()
+                    q.qless_tsqr_r(Xs, R=Rs, work=ws)
+
+                q.timing_reset()
+                q.timing_enable(True)
+                t_ms, _ = time_calls(f, steps, 2)
+                q.timing_enable(False)
+                k_ms, k_cnt = q.timing_read("tsqr_stage1")
+                q.timing_reset()
+                k_avg = k_ms / max(k_cnt, 1)
+                gbs = tsqr_bytes(m, ns) / (k_avg * 1e-3) / 1e9
+                rec.update({"tsqr_ms": round(k_avg, 5), "tsqr_GBps": round(gbs, 1),
+                            "tsqr_frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                            "tsqr_TFps": round(tsqr_flops(m, ns) / (k_avg * 1e-3) / 1e12, 2),
+                            "tsqr_frac_fp64": round(tsqr_flops(m, ns) / (k_avg * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)})
+                if flush is None:
+                    rec["tsqr_step_ms"] = round(t_ms, 5)
+                c_ms, _ = time_calls(lambda: q.cholqr2_r(Xs, work=None), max(3, steps // 4), 1)
+                rec.update({"cholqr2_ms": round(c_ms, 5),
+                            "cholqr2_GBps": round(gram2_bytes(m, ns) / (c_ms * 1e-3) / 1e9, 1),
+                            "cholqr2_TFps": round(5.0 * m * ns * ns / (c_ms * 1e-3) / 1e12, 2)})
+                del flush
+            del Xs, ws
+            torch.cuda.empty_cache()
+        sweep.append(rec)
+        log(json.dumps(rec))
+    return sweep
+
+
+def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
+    """512 matrices (m log-uniform [1e4, 1e7], n in {4, 8, 16, 32}), each an
+    iid N(0,1) window of one device pool, in one persistent launch (eager and
+    replayed from a captured graph) vs one qless_tsqr_r launch per matrix."""
+    import numpy as np
+    import torch
+    shapes = wl.batched_shapes(count, seed)
+    pool_len = max(m * n for m, n in shapes)
+    pool = wl.gaussian_torch(pool_len, 1, seed=seed, device=dev).view(-1)
+    g = wl.rng(seed + 1)
+    Xs = []
+    for m, n in shapes:
+        off = int(g.integers(0, pool_len - m * n + 1))
+        Xs.append(pool[off:off + m * n].view(m, n))
+    total_bytes = sum(8 * m * n for m, n in shapes)
+    log("batched: %d matrices, %.1f GB" % (count, total_bytes / 1e9))
+    plan = q.BatchPlan(Xs)
+    plan.run()
+    torch.cuda.synchronize()
+    t_eager, _ = time_calls(plan.run, 5, 1)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.run()
+    torch.cuda.synchronize()
+    t_graph, _ = time_calls(graph.replay, 5, 1)
+    Rb = [R.clone() for R in plan.Rs]
+    # one launch per matrix, same stream, workspace sized for the largest
+    wmax = max(q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, m, n) for m, n in shapes)
+    work = torch.empty(wmax, dtype=torch.uint8, device=dev)
+    Rs1 = [torch.empty((n, n), dtype=torch.float64, device=dev) for _, n in shapes]
+
+    def singles():
+        for X, R in zip(Xs, Rs1):
+            q.qless_tsqr_r(X, R=R, work=work)
+    t_single, _ = time_calls(singles, 3, 1)
+    err = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(Rb, Rs1))
+    res = {"matrices": count, "total_GB": round(total_bytes / 1e9, 2), "tiles": plan.tiles,
+           "batched_ms": round(t_eager, 3), "batched_graph_ms": round(t_graph, 3),
+           "single_launches_ms": round(t_single, 3),
+           "solves_per_s": round(count / (t_graph * 1e-3), 1),
+           "solves_per_s_single": round(count / (t_single * 1e-3), 1),
+           "GBps": round(total_bytes / (t_graph * 1e-3) / 1e9, 1),
+           "max_rel_diff_vs_single": err}
+    plan.close()
+    log("batched: %s" % json.dumps(res))
+    del Xs, pool, work
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_served(q, dev, log, count: int):
+    """Poisson least-squares requests [A b] (m log-uniform [1e4, 5e7], n in
+    3..47): continuous-batching server vs one request per launch, at 0.8x the
+    measured one-at-a-time capacity."""
+    import torch
+    from paper_2603_20889_amd.server import FifoServer, GpuExecutor, LstsqServer, make_requests
+    probe = make_requests(24, rate_per_s=1e9, seed=55)
+    ex = GpuExecutor(dev)
+    t0 = time.perf_counter()
+    FifoServer(ex).run(probe, realtime=False)
+    torch.cuda.synchronize()
+    capacity = len(probe) / (time.perf_counter() - t0)
+    rate = 0.8 * capacity
+    log("served: one-at-a-time capacity %.1f req/s, offered %.1f req/s" % (capacity, rate))
+    reqs = make_requests(count, rate_per_s=rate, seed=5)
+    srv = LstsqServer(GpuExecutor(dev), hbm_budget_bytes=96 << 30, step_bytes=2 << 30, max_active=64)
+    st = srv.run(reqs, realtime=True)
+    reqs2 = make_requests(count, rate_per_s=rate, seed=5)
+    st_fifo = FifoServer(GpuExecutor(dev)).run(reqs2, realtime=True)
+    bad = sum(1 for r in reqs if r.info != 0)
+    res = {"requests": count, "offered_rate_per_s": round(rate, 1), "capacity_one_at_a_time_per_s": round(capacity, 1),
+           "server": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()},
+           "fifo_one_per_launch": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st_fifo.items()},
+           "failed": bad}
+    log("served: %s" % json.dumps(res))
+    return res
 
 
 if __name__ == "__main__":

@@ -81,10 +81,10 @@ batched_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles
                double* __restrict__ slots, int* __restrict__ counters, int* __restrict__ queue, int np_max) {
     extern __shared__ double lds[];
     const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
     const int64_t w = (int64_t)blockIdx.x * kBatchWpb + wib;
     if (w >= nwaves) return;
-    double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2);
+    double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2 + np_max);
     while (true) {
         int t = 0;
         if (lane == 0) t = __hip_atomic_fetch_add(queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -212,7 +212,7 @@ int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStrea
     char* b = static_cast<char*>(work);
     int* counters = reinterpret_cast<int*>(b + p->off_counters);
     int* queue = counters + (p->counter_ints - 2);
-    const size_t lds = (size_t)kBatchWpb * (p->np_max * (p->np_max + 1) / 2) * sizeof(double);
+    const size_t lds = (size_t)kBatchWpb * (p->np_max * (p->np_max + 1) / 2 + p->np_max) * sizeof(double);
     const int64_t blocks = ceil_div(p->nwaves, kBatchWpb);
     hipLaunchKernelGGL(batched_kernel, dim3((unsigned)blocks), dim3(64 * kBatchWpb), lds, s,
                        reinterpret_cast<const BatchMat*>(b), reinterpret_cast<const int2*>(b + p->off_tiles),

@@ -15,7 +15,7 @@
 // matrix.  At the end the G groups are summed and each wavefront writes its
 // n x n partial to the workspace; gram_sum adds the partials in a fixed order
 // (no atomics, so results are reproducible bit for bit).
-#include "qless_internal.h"
+#include "tsqr_kernels.h"
 
 namespace qless {
 namespace {
@@ -35,7 +35,7 @@ gram_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t
     using S = GramShape<NP>;
     __shared__ double slab[4][2][S::SR * S::LD];
     const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
     const int64_t w = (int64_t)blockIdx.x * 4 + wib;
     if (w >= nwaves) return;
     const int g = lane / NP;
@@ -105,6 +105,83 @@ gram_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t
     }
 }
 
+// Row layout for n <= 8: each lane holds RPL full rows of a 64*RPL-row panel
+// (the TSQR stage-1 loads), forms y = x M one row at a time (M from LDS,
+// broadcast reads) and accumulates the n(n+1)/2 products y_a y_b of the upper
+// triangle in registers.  Nothing crosses lanes until the end, where one
+// transposed butterfly sums all accumulators over the wavefront.
+template <int NP, int RPL, bool HAS_M>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+gram_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                 int64_t nwaves, const double* __restrict__ M, double* __restrict__ Cpart) {
+    constexpr int K = NP * (NP + 1) / 2;
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    __shared__ double Ms[NP * NP];
+    const int lane = lane_id();
+    if (HAS_M) {
+        for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
+            const int k = e / NP, c = e % NP;
+            Ms[e] = (k < n && c < n) ? M[(int64_t)k * n + c] : 0.0;
+        }
+        __syncthreads();
+    }
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nwaves) return;
+    double acc[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) acc[t] = 0.0;
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        double x[RPL][NP];
+        tsqr_detail::load_panel_1d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
+        if (HAS_M) {
+            // y = x M for the lane's RPL rows, one column of M at a time so that
+            // each M entry is read once from LDS and used for every row
+            double y[RPL][NP];
+#pragma unroll
+            for (int c = 0; c < NP; ++c) {
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) y[i][c] = 0.0;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const double mkc = Ms[k * NP + c];
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) y[i][c] = fma(x[i][k], mkc, y[i][c]);
+                }
+                asm volatile("" ::: "memory");   // keep the M reads of later columns here (register pressure)
+            }
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+#pragma unroll
+                for (int c = 0; c < NP; ++c) x[i][c] = y[i][c];
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NP; ++a)
+#pragma unroll
+                for (int b = a; b < NP; ++b, ++t) acc[t] = fma(x[i][a], x[i][b], acc[t]);
+        }
+    }
+    double tot[K];
+    wave_sum_multi<K>(acc, tot, lane);
+    if (lane < n) {
+        // row `lane` of the symmetric partial
+        double* out = Cpart + w * (int64_t)n * n + (int64_t)lane * n;
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a)
+#pragma unroll
+            for (int b = a; b < NP; ++b, ++t) {
+                if (a == lane && b < n) out[b] = tot[t];
+                if (b == lane && a < n) out[a] = tot[t];
+            }
+    }
+}
+
 // C = sum over w < k of Cpart[w] (n x n), in a fixed order: each of the
 // PARTS threads of an entry sums a contiguous range of w sequentially, and
 // the PARTS subtotals are added pairwise in LDS.
@@ -133,8 +210,15 @@ gram_sum_kernel(const double* __restrict__ Cpart, int64_t k, int n, double* __re
 template <int NP, bool HAS_M>
 hipError_t launch_gram_t(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
                          const double* M, double* Cpart, hipStream_t s) {
-    hipLaunchKernelGGL((gram_kernel<NP, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n, ldx,
-                       rpw, nw, M, Cpart);
+    if constexpr (NP <= 8) {
+        // with the fused multiply, half the rows per lane leave room for y = x M
+        constexpr int RPL = HAS_M ? (NP >= 32 ? 1 : 32 / NP) : 64 / NP;
+        hipLaunchKernelGGL((gram_rows_kernel<NP, RPL, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s,
+                           X, m, n, ldx, rpw, nw, M, Cpart);
+    } else {
+        hipLaunchKernelGGL((gram_kernel<NP, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n,
+                           ldx, rpw, nw, M, Cpart);
+    }
     return hipGetLastError();
 }
 
@@ -149,7 +233,7 @@ int gram_npad(int64_t n) {
 GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus) {
     GramPlan p;
     p.npad = gram_npad(n);
-    const int64_t slab = 512 / p.npad;
+    const int64_t slab = p.npad <= 8 ? (int64_t)kWave * (64 / p.npad) : 512 / p.npad;
     const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * 8;
     int64_t rpw = ceil_div(m > 0 ? m : 1, max_waves);
     rpw = ceil_div(rpw, slab) * slab;

@@ -44,6 +44,35 @@ constexpr int tri_size() {
 }
 
 
+// Scalars of the reflector that maps (alpha, x) with |x|^2 = s > 0 to
+// (beta, 0): nrm = sqrt(alpha^2 + s), beta = -sign(alpha) nrm (sign(+0) = +),
+// u0 = alpha - beta (its pivot entry) and gamma = 2 / (u^T u) =
+// 1 / (nrm (nrm + |alpha|)).  The square root and the reciprocal start from
+// the hardware estimates (v_rsq_f64, v_rcp_f64) and take two Newton steps
+// each, which leaves a few units in the last place -- far inside the
+// tolerance -- at a third of the instructions of the IEEE-rounded sequences.
+__device__ __forceinline__ void reflector_scalars(double alpha, double s, double& beta, double& u0, double& gamma) {
+    const double q = fma(alpha, alpha, s);
+    const double h = 0.5 * q;
+    double y = __builtin_amdgcn_rsq(q);          // ~ q^{-1/2}
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {              // y <- y (3/2 - q y^2 / 2)
+        const double e = fma(-h, y * y, 0.5);
+        y = fma(y, e, y);
+    }
+    const double nrm = q * y;
+    beta = (alpha >= 0.0) ? -nrm : nrm;
+    u0 = alpha - beta;
+    const double d = nrm * (nrm + fabs(alpha));
+    double r = __builtin_amdgcn_rcp(d);           // ~ 1/d
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {              // r <- r (2 - d r)
+        const double e = fma(-d, r, 1.0);
+        r = fma(r, e, r);
+    }
+    gamma = r;
+}
+
 // Fold one panel for NP <= 16: the column loop is a compile-time recursion so
 // that every register index is a constant.  Step J forms the K = NP - J
 // partial dot products of column J with columns J..NP-1 in each lane, sums
@@ -59,13 +88,39 @@ struct PanelPrefetch {
     int so;                        // row-stripe offset (bytes)
 };
 
+// Per-lane value index after the transposed butterfly: byte K-1 of the
+// packed words is red_origin(K, lane), the value whose wavefront total this
+// lane holds when K values are summed.
+template <int NP>
+struct LaneOrigins {
+    uint32_t w[(NP + 3) / 4];
+    __device__ __forceinline__ void init(int lane) {
+#pragma unroll
+        for (int q = 0; q < (NP + 3) / 4; ++q) w[q] = 0u;
+#pragma unroll
+        for (int K = 1; K <= NP; ++K) w[(K - 1) >> 2] |= (uint32_t)red_origin(K, lane) << (8 * ((K - 1) & 3));
+    }
+    template <int K>
+    __device__ __forceinline__ int get() const {
+        return (int)((w[(K - 1) >> 2] >> (8 * ((K - 1) & 3))) & 0xFFu);
+    }
+};
+
+// Step J of the fold (n <= 16).  The K = NP - J partial dot products of
+// column J with columns J..NP-1 are summed over the wavefront by one
+// transposed butterfly, after which every lane holds the total of one value
+// v.  Each lane then finishes the work of its own value: the update
+// coefficient of column J+v and the new R_{J,J+v} (R_JJ = beta for v = 0),
+// written back to LDS, and the coefficients are shared through LDS
+// broadcast reads.  The reflector scalars (norm, beta, gamma) are
+// wave-uniform.
 template <int NP, int RPL, int J>
 struct FoldStep {
-    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, int lane,
-                                               const PanelPrefetch& pf) {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, double* __restrict__ Cw,
+                                               const LaneOrigins<NP>& org, int lane, const PanelPrefetch& pf) {
         if constexpr (J < NP) {
             constexpr int K = NP - J;
-            double p[K], tot[K], rj[K];
+            double p[K];
 #pragma unroll
             for (int t = 0; t < K; ++t) {
                 double s = 0.0;
@@ -73,37 +128,36 @@ struct FoldStep {
                 for (int i = 0; i < RPL; ++i) s = fma(x[i][J], x[i][J + t], s);
                 p[t] = s;
             }
-#pragma unroll
-            for (int t = 0; t < K; ++t) rj[t] = Rw[tri_row<NP>(J) + t];
-            wave_sum_multi<K>(p, tot, lane);
-            const double alpha = rj[0];
-            const double s = tot[0];
+            const double alpha = Rw[tri_row<NP>(J)];
+            red_stages<K, 0>(p, lane);                  // p[0]: total of value v in this lane
+            const int v = org.template get<K>();
+            const double r = Rw[tri_row<NP>(J) + v];
+            const double s = readlane_f64(p[0], red_locate(K, 0));
             if (s != 0.0) {
-                const double nrm = sqrt(fma(alpha, alpha, s));
-                const double beta = (alpha >= 0.0) ? -nrm : nrm;
-                const double u0 = alpha - beta;
-                const double gamma = 1.0 / (nrm * (nrm + fabs(alpha)));
+                double beta, u0, gamma;
+                reflector_scalars(alpha, s, beta, u0, gamma);
+                const double coef = gamma * fma(u0, r, p[0]);   // gamma * (u^T column J+v)
+                Rw[tri_row<NP>(J) + v] = (v == 0) ? beta : fma(-coef, u0, r);
+                if constexpr (K > 1) {
+                    Cw[v] = coef;                        // every holder of v writes the same value
+                    __builtin_amdgcn_wave_barrier();
+                    double c[K];
 #pragma unroll
-                for (int t = 1; t < K; ++t) {
-                    const double coef = gamma * fma(u0, rj[t], tot[t]);
+                    for (int t = 1; t < K; ++t) c[t] = Cw[t];
 #pragma unroll
-                    for (int i = 0; i < RPL; ++i) x[i][J + t] = fma(-coef, x[i][J], x[i][J + t]);
-                    rj[t] = fma(-coef, u0, rj[t]);
-                }
-                rj[0] = beta;
-                if (lane == 0) {
+                    for (int t = 1; t < K; ++t)
 #pragma unroll
-                    for (int t = 0; t < K; ++t) Rw[tri_row<NP>(J) + t] = rj[t];
+                        for (int i = 0; i < RPL; ++i) x[i][J + t] = fma(-c[t], x[i][J], x[i][J + t]);
                 }
             }
             if constexpr (J % 2 == 1) {
                 if (pf.on) {
 #pragma unroll
                     for (int i = 0; i < RPL; ++i) {
-                        const f64x2 v = __builtin_bit_cast(
+                        const f64x2 v2 = __builtin_bit_cast(
                             f64x2, __builtin_amdgcn_raw_buffer_load_b128(pf.rs, pf.vo + (J - 1) * 8, pf.so * i, 0));
-                        x[i][J - 1] = v[0];
-                        x[i][J] = v[1];
+                        x[i][J - 1] = v2[0];
+                        x[i][J] = v2[1];
                     }
                 }
             } else if constexpr (J == NP - 1) {
@@ -114,14 +168,14 @@ struct FoldStep {
                             double, __builtin_amdgcn_raw_buffer_load_b64(pf.rs, pf.vo + J * 8, pf.so * i, 0));
                 }
             }
-            FoldStep<NP, RPL, J + 1>::run(x, Rw, lane, pf);
+            FoldStep<NP, RPL, J + 1>::run(x, Rw, Cw, org, lane, pf);
         }
     }
 };
 
 template <int NP>
 constexpr int waves_per_block() {
-    return (tri_size<NP>() * 8 * 4 <= 65536) ? 4 : 2;
+    return ((tri_size<NP>() + NP) * 8 * 4 <= 65536) ? 4 : 2;
 }
 
 // Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
@@ -175,6 +229,9 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
     constexpr int64_t PANEL = (int64_t)kWave * RPL;
     if (r_begin >= r_end) return;
     const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
+    LaneOrigins<NP> org;
+    org.init(lane);
+    double* Cw = Rw + tri_size<NP>();   // per-wavefront coefficient exchange
     double x[RPL][NP];
     load_panel_1d<NP, RPL>(x, X, n, ldx, r_begin, r_end, fast, lane);
     for (int64_t base = r_begin;;) {
@@ -185,7 +242,7 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
                                                   0x7FFFFFFF, 0x00020000);
         pf.vo = lane * (int)(ldx * 8);
         pf.so = (int)(ldx * 8 * kWave);
-        FoldStep<NP, RPL, 0>::run(x, Rw, lane, pf);
+        FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane, pf);
         if (next >= r_end) break;
         if (!pf.on) load_panel_1d<NP, RPL>(x, X, n, ldx, next, r_end, false, lane);
         base = next;
@@ -250,10 +307,8 @@ struct FoldStep2D {
             const double s = readlane_f64(p[0], cgJ);   // |panel part of column J|^2
             const double alpha = Rw[tri_row<NP>(J)];
             if (s != 0.0) {
-                const double nrm = sqrt(fma(alpha, alpha, s));
-                const double beta = (alpha >= 0.0) ? -nrm : nrm;
-                const double u0 = alpha - beta;
-                const double gamma = 1.0 / (nrm * (nrm + fabs(alpha)));
+                double beta, u0, gamma;
+                reflector_scalars(alpha, s, beta, u0, gamma);
 #pragma unroll
                 for (int a = 0; a < A; ++a) {
                     const int c = cg + kG2 * (uJ + a);
@@ -408,9 +463,9 @@ tsqr_fused_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, i
                   int64_t nwaves, double* __restrict__ R, int64_t ldr, double* __restrict__ slots,
                   unsigned long long* __restrict__ counters, int fan_in, unsigned long long tag) {
     constexpr int WPB = waves_per_block<NP>();
-    __shared__ double Rsh[WPB][tri_size<NP>()];
+    __shared__ double Rsh[WPB][tri_size<NP>() + NP];
     const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
     const int64_t w = (int64_t)blockIdx.x * WPB + wib;
     if (w >= nwaves) return;
     double* Rw = Rsh[wib];
