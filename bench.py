@@ -255,11 +255,11 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25):
             rec["cholqr2_info_k%d" % k] = int(info.item())
             if k == 4:
                 steps = 20 if ns <= 16 else 5
-                flush = torch.empty(2 ** 27, dtype=torch.float64, device=dev) if ns <= 4 else None
+                flush = torch.ones(2 ** 27, dtype=torch.float64, device=dev) if ns <= 4 else None
 
                 def f():
-                    if flush is not None:      # evict the 256 MB MALL between calls: 1 GiB write
-                        flush.zero_()
+                    if flush is not None:      # evict the 256 MB MALL between calls: read 1 GiB
+                        torch.sum(flush)       # (a read leaves no dirty lines to write back)
                     q.qless_tsqr_r(Xs, R=Rs, work=ws)
 
                 q.timing_reset()

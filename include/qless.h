@@ -152,7 +152,8 @@ int qless_tune_get(int64_t n, int32_t *waves_per_cu, int32_t *fan_in, int32_t *r
 
 /*
  * Batched Q-less TSQR: many independent matrices of uneven m and n in one
- * persistent launch (Alg. 2 applied to each).  Descriptor fields follow
+ * persistent stage-1 launch plus one launch per tree level (Alg. 2 applied
+ * to each).  Descriptor fields follow
  * qless_tsqr_r: X (device, m x n row-major, ldx >= n; may be NULL when
  * m == 0), R (device, n x n, ldr >= n), 1 <= n <= QLESS_MAX_N.  With
  * accumulate != 0 the matrix's current R (any upper-triangular n x n, e.g.
@@ -169,7 +170,7 @@ typedef struct {
 
 /* Opaque host-side plan: tiles every matrix into row ranges of about
  * tile_bytes (<= 0: 4 MiB) and orders them longest first; waves_per_cu
- * (<= 0: 8) sets the persistent grid.  The descriptors are copied; their
+ * (<= 0: 8) sets the persistent grid (wavefronts per compute unit).  The descriptors are copied; their
  * device pointers must stay valid while the plan is used.  Returns
  * QLESS_ERR_ARG / QLESS_ERR_UNSUPPORTED for an invalid descriptor. */
 typedef struct qless_batch_plan qless_batch_plan;
@@ -180,13 +181,14 @@ void qless_batch_plan_destroy(qless_batch_plan *plan);
 size_t qless_batch_plan_workspace_bytes(const qless_batch_plan *plan);
 /* Number of row tiles in the plan. */
 int64_t qless_batch_plan_tiles(const qless_batch_plan *plan);
-/* Copy the plan's tables into `work` and zero its counters; synchronises
- * `stream`.  Call once per workspace before the first qless_tsqr_r_batched. */
+/* Copy the plan's tables (matrices, tiles, tree groups) into `work`;
+ * synchronises `stream`.  Call once per workspace before the first
+ * qless_tsqr_r_batched. */
 int qless_batch_plan_upload(const qless_batch_plan *plan, void *work, size_t work_bytes, hipStream_t stream);
-/* One launch computing every matrix's R.  Allocates nothing, copies nothing
- * from the host and leaves the workspace ready for the next call, so it can
- * be captured in a hipGraph and replayed.  Calls sharing a workspace must not
- * overlap. */
+/* Enqueue the launches computing every matrix's R (1 + tree levels, all on
+ * `stream`).  Allocates nothing, copies nothing from the host, issues no
+ * memset and keeps no state between calls, so the sequence can be captured
+ * in a hipGraph and replayed.  Calls sharing a workspace must not overlap. */
 int qless_tsqr_r_batched(const qless_batch_plan *plan, void *work, size_t work_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------- timing hooks */

@@ -305,7 +305,8 @@ class BatchPlan:
 
 
 def qless_tsqr_r_batched(Xs, **kw):
-    """R of every matrix of the list ``Xs`` in one persistent launch."""
+    """R of every matrix of the list ``Xs``: one persistent stage-1 launch plus
+    one launch per tree level."""
     plan = BatchPlan(Xs, **kw)
     Rs = plan.run()
     import torch

@@ -1,19 +1,20 @@
 // Batched Q-less TSQR: many independent tall-skinny matrices of uneven m and
-// n in ONE persistent launch (paper Alg. 2 applied per matrix).
+// n in one persistent stage-1 launch plus one launch per tree level (paper
+// Alg. 2 applied per matrix).
 //
-// The host plan cuts every matrix into row tiles (about tile_bytes each) and
-// orders all tiles longest first.  A fixed grid of wavefronts pulls tiles
-// from a device queue (one atomic counter).  A wavefront folds its tile into
-// an R with the same per-n code as qless_tsqr_r, writes it to the matrix's
-// level-0 slot and increments the counter of its group of kFanIn siblings;
-// the wavefront that completes a group folds the group's stacked triangles
-// (the tree step of Alg. 2) into the next level, and the one that completes
-// the root writes the matrix's sign-normalised R.  No wavefront ever waits
-// for another, so the grid drains whatever the residency; counters reset
-// themselves, so the launch can be replayed from a captured graph with no
-// memset in between.  Optionally the previous contents of a matrix's R are
-// stacked into its root (R([R_old; X])), which is how a caller keeps a
-// running R over chunks of rows.
+// The host plan cuts every matrix into row tiles (about tile_bytes each),
+// orders all tiles longest first and lists the tree groups of every level.
+// Stage 1: a fixed grid of wavefronts takes the tiles in turn (wavefront w
+// takes tiles w, w + W, w + 2W, ...); each folds its tile into an R with the
+// same per-n code as qless_tsqr_r and writes it to the matrix's level-0 slot
+// (a matrix of one tile writes its final R at once).  Tree level l: the
+// groups of fan_in stacked triangles of every matrix that still has more
+// than one are folded by the same grid, level l+1 slots or, for a root, the
+// matrix's sign-normalised R.  Wavefronts never wait for one another, and no
+// state survives a launch, so a captured graph of the sequence replays
+// as is.  Optionally the previous contents of a matrix's R are stacked into
+// its root (R([R_old; X])), which is how a caller keeps a running R over
+// chunks of rows.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -22,93 +23,97 @@
 
 struct qless_batch_plan {
     std::vector<qless::BatchMat> mats;
-    std::vector<int2> tiles;
+    std::vector<int2> tiles;                  // (matrix, tile) longest first
+    std::vector<qless::BatchGroup> groups;    // tree groups, level by level
+    std::vector<int64_t> level_end;           // groups [level_end[l-1], level_end[l]) form level l
     int np_max = 1;
     int64_t slot_doubles = 0;
-    int64_t counter_ints = 0;
-    size_t off_tiles = 0, off_counters = 0, off_slots = 0, bytes = 0;
+    size_t off_tiles = 0, off_groups = 0, off_slots = 0, bytes = 0;
     int64_t nwaves = 0;
+    int waves_cap = 0;
 };
 
 namespace qless {
 namespace {
 
 constexpr int kFanIn = 16;
-constexpr int kBatchWpb = 2;  // wavefronts per workgroup of the batched kernel
-
-__device__ __forceinline__ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+constexpr int kBatchWpb = 2;  // wavefronts per workgroup of the batched kernels
 
 template <int NP, int RPL>
-__device__ __forceinline__ void batch_tile(const BatchMat& M, int t, double* __restrict__ Rw, double* __restrict__ slots,
-                           int* __restrict__ counters, int lane) {
+__device__ __forceinline__ void batch_stage_tile(const BatchMat& M, int t, double* __restrict__ Rw,
+                                                 double* __restrict__ slots, int lane) {
     using namespace tsqr_detail;
-    const int n = M.n;
-    const int64_t nn = (int64_t)n * n;
     zero_r<NP>(Rw, lane);
     const int64_t r0 = (int64_t)t * M.tile_rows;
     const int64_t r1 = (r0 + M.tile_rows < M.m) ? r0 + M.tile_rows : M.m;
-    fold_rows<NP, RPL>(M.X, n, M.ldx, r0, r1, Rw, lane);
-    int64_t count = M.ntiles, idx = t, sbase = M.slot_base, cbase = M.cnt_base;
-    while (true) {
-        if (count == 1) {
-            if (M.accumulate) fold_rows<NP, RPL>(M.R, n, M.ldr, 0, n, Rw, lane);
-            store_r<NP>(Rw, n, M.R, M.ldr, true, lane);
-            return;
-        }
-        store_r<NP>(Rw, n, slots + sbase + idx * nn, n, false, lane);
-        __threadfence();
-        const int64_t g = idx / kFanIn;
-        const int64_t gsize = (count - g * kFanIn < kFanIn) ? count - g * kFanIn : kFanIn;
-        int old = 0;
-        if (lane == 0)
-            old = __hip_atomic_fetch_add(counters + cbase + g, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        old = __builtin_amdgcn_readfirstlane(old);
-        if (old != gsize - 1) return;     // a sibling is still running; it will continue the tree
-        if (lane == 0) __hip_atomic_store(counters + cbase + g, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        zero_r<NP>(Rw, lane);
-        fold_rows<NP, RPL>(slots + sbase + g * kFanIn * nn, n, n, 0, gsize * n, Rw, lane);
-        sbase += count * nn;
-        cbase += cdiv(count, kFanIn);
-        idx = g;
-        count = cdiv(count, kFanIn);
+    fold_rows<NP, RPL>(M.X, M.n, M.ldx, r0, r1, Rw, lane);
+    if (M.ntiles == 1) {
+        if (M.accumulate) fold_rows<NP, RPL>(M.R, M.n, M.ldr, 0, M.n, Rw, lane);
+        store_r<NP>(Rw, M.n, M.R, M.ldr, true, lane);
+    } else {
+        store_r<NP>(Rw, M.n, slots + M.slot_base + (int64_t)t * M.n * M.n, M.n, false, lane);
     }
 }
 
-// queue[0]: next tile, queue[1]: wavefronts finished (both reset by the last wavefront)
+template <int NP, int RPL>
+__device__ __forceinline__ void batch_tree_group(const BatchMat& M, const BatchGroup& G, double* __restrict__ Rw,
+                                                 double* __restrict__ slots, int lane) {
+    using namespace tsqr_detail;
+    zero_r<NP>(Rw, lane);
+    fold_rows<NP, RPL>(slots + G.src, M.n, M.n, 0, (int64_t)G.gsize * M.n, Rw, lane);
+    if (G.dst < 0) {
+        if (M.accumulate) fold_rows<NP, RPL>(M.R, M.n, M.ldr, 0, M.n, Rw, lane);
+        store_r<NP>(Rw, M.n, M.R, M.ldr, true, lane);
+    } else {
+        store_r<NP>(Rw, M.n, slots + G.dst, M.n, false, lane);
+    }
+}
+
+// Instance per padded width: (NP, rows per lane) as in the single-matrix path.
+#define QLESS_BATCH_SWITCH(np, CALL)           \
+    switch (np) {                              \
+        case 1: CALL(1, 64); break;            \
+        case 2: CALL(2, 32); break;            \
+        case 4: CALL(4, 16); break;            \
+        case 8: CALL(8, 8); break;             \
+        case 16: CALL(16, 4); break;           \
+        case 32: CALL(32, 12); break;          \
+        default: CALL(64, 5); break;           \
+    }
+
 __global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
-batched_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles, int64_t ntiles, int64_t nwaves,
-               double* __restrict__ slots, int* __restrict__ counters, int* __restrict__ queue, int np_max) {
+batched_stage_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles, int64_t ntiles,
+                     int64_t nwaves, double* __restrict__ slots, int np_max) {
     extern __shared__ double lds[];
     const int lane = lane_id();
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
     const int64_t w = (int64_t)blockIdx.x * kBatchWpb + wib;
     if (w >= nwaves) return;
     double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2 + np_max);
-    while (true) {
-        int t = 0;
-        if (lane == 0) t = __hip_atomic_fetch_add(queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= ntiles) break;
+    for (int64_t t = w; t < ntiles; t += nwaves) {
         const int2 tl = tiles[t];
         const BatchMat M = mats[tl.x];
-        switch (M.np) {
-            case 1: batch_tile<1, 64>(M, tl.y, Rw, slots, counters, lane); break;
-            case 2: batch_tile<2, 32>(M, tl.y, Rw, slots, counters, lane); break;
-            case 4: batch_tile<4, 16>(M, tl.y, Rw, slots, counters, lane); break;
-            case 8: batch_tile<8, 8>(M, tl.y, Rw, slots, counters, lane); break;
-            case 16: batch_tile<16, 4>(M, tl.y, Rw, slots, counters, lane); break;
-            case 32: batch_tile<32, 12>(M, tl.y, Rw, slots, counters, lane); break;
-            default: batch_tile<64, 5>(M, tl.y, Rw, slots, counters, lane); break;
-        }
+#define QLESS_STAGE_CALL(NP, RPL) batch_stage_tile<NP, RPL>(M, tl.y, Rw, slots, lane)
+        QLESS_BATCH_SWITCH(M.np, QLESS_STAGE_CALL)
+#undef QLESS_STAGE_CALL
     }
-    // the last wavefront to leave resets the queue for the next launch
-    if (lane == 0) {
-        const int done = __hip_atomic_fetch_add(queue + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (done == (int)nwaves - 1) {
-            __hip_atomic_store(queue, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(queue + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+}
+
+__global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
+batched_tree_kernel(const BatchMat* __restrict__ mats, const BatchGroup* __restrict__ groups, int64_t ngroups,
+                    int64_t nwaves, double* __restrict__ slots, int np_max) {
+    extern __shared__ double lds[];
+    const int lane = lane_id();
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * kBatchWpb + wib;
+    if (w >= nwaves) return;
+    double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2 + np_max);
+    for (int64_t q = w; q < ngroups; q += nwaves) {
+        const BatchGroup G = groups[q];
+        const BatchMat M = mats[G.mat];
+#define QLESS_TREE_CALL(NP, RPL) batch_tree_group<NP, RPL>(M, G, Rw, slots, lane)
+        QLESS_BATCH_SWITCH(M.np, QLESS_TREE_CALL)
+#undef QLESS_TREE_CALL
     }
 }
 
@@ -146,8 +151,9 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
     }
     qless_batch_plan* p = new (std::nothrow) qless_batch_plan;
     if (!p) return QLESS_ERR_ARG;
-    int64_t slots = 0, cnts = 0;
+    int64_t slots = 0;
     std::vector<std::pair<int64_t, int2>> order;
+    std::vector<std::vector<BatchGroup>> levels;
     for (int32_t i = 0; i < count; ++i) {
         BatchMat M{};
         M.X = d[i].X;
@@ -164,10 +170,26 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
         M.tile_rows = tr;
         M.ntiles = (int)std::max<int64_t>(1, ceil_div(d[i].m, tr));
         M.slot_base = slots;
-        M.cnt_base = cnts;
-        for (int64_t c = M.ntiles; c > 1; c = ceil_div(c, kFanIn)) {
-            slots += c * d[i].n * d[i].n;
-            cnts += ceil_div(c, kFanIn);
+        // slots of level l hold the c_l triangles of that level (c_0 = ntiles);
+        // the root (c_l = 1) is written to R instead
+        const int64_t nn = d[i].n * d[i].n;
+        int64_t base = slots, c = M.ntiles;
+        if (c > 1) slots += c * nn;
+        for (int l = 1; c > 1; ++l) {
+            const int64_t cn = ceil_div(c, kFanIn);
+            const int64_t next_base = slots;
+            if (cn > 1) slots += cn * nn;
+            if ((int)levels.size() < l) levels.resize(l);
+            for (int64_t g = 0; g < cn; ++g) {
+                BatchGroup G;
+                G.src = base + g * kFanIn * nn;
+                G.dst = cn == 1 ? -1 : next_base + g * nn;
+                G.mat = i;
+                G.gsize = (int)std::min<int64_t>(kFanIn, c - g * kFanIn);
+                levels[l - 1].push_back(G);
+            }
+            base = next_base;
+            c = cn;
         }
         p->np_max = std::max(p->np_max, M.np);
         p->mats.push_back(M);
@@ -180,14 +202,18 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
                      [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) { return a.first > b.first; });
     p->tiles.reserve(order.size());
     for (auto& o : order) p->tiles.push_back(o.second);
+    for (auto& lv : levels) {
+        p->groups.insert(p->groups.end(), lv.begin(), lv.end());
+        p->level_end.push_back((int64_t)p->groups.size());
+    }
     p->slot_doubles = slots;
-    p->counter_ints = cnts + 2;
     p->off_tiles = align_up(p->mats.size() * sizeof(BatchMat), 256);
-    p->off_counters = p->off_tiles + align_up(p->tiles.size() * sizeof(int2), 256);
-    p->off_slots = p->off_counters + align_up((size_t)p->counter_ints * sizeof(int), 256);
+    p->off_groups = p->off_tiles + align_up(p->tiles.size() * sizeof(int2), 256);
+    p->off_slots = p->off_groups + align_up(std::max<size_t>(p->groups.size(), 1) * sizeof(BatchGroup), 256);
     p->bytes = p->off_slots + align_up((size_t)std::max<int64_t>(slots, 1) * sizeof(double), 256);
     const DeviceInfo& di = current_device_info();
-    p->nwaves = std::min<int64_t>((int64_t)p->tiles.size(), (int64_t)di.num_cus * waves_per_cu);
+    p->waves_cap = di.num_cus * waves_per_cu;
+    p->nwaves = std::min<int64_t>((int64_t)p->tiles.size(), (int64_t)p->waves_cap);
     *out = p;
     return QLESS_OK;
 }
@@ -200,7 +226,9 @@ int batch_plan_upload(const qless_batch_plan* p, void* work, size_t work_bytes, 
     hipError_t e = hipMemcpyAsync(b, p->mats.data(), p->mats.size() * sizeof(BatchMat), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b + p->off_tiles, p->tiles.data(), p->tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(b + p->off_counters, 0, (size_t)p->counter_ints * sizeof(int), s);
+    if (e == hipSuccess && !p->groups.empty())
+        e = hipMemcpyAsync(b + p->off_groups, p->groups.data(), p->groups.size() * sizeof(BatchGroup),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the plan's host arrays may be reused right after
     return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
@@ -210,15 +238,24 @@ int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStrea
     if (work == nullptr || (reinterpret_cast<uintptr_t>(work) & 255u) || work_bytes < p->bytes)
         return QLESS_ERR_WORKSPACE;
     char* b = static_cast<char*>(work);
-    int* counters = reinterpret_cast<int*>(b + p->off_counters);
-    int* queue = counters + (p->counter_ints - 2);
+    const BatchMat* mats = reinterpret_cast<const BatchMat*>(b);
+    double* slots = reinterpret_cast<double*>(b + p->off_slots);
     const size_t lds = (size_t)kBatchWpb * (p->np_max * (p->np_max + 1) / 2 + p->np_max) * sizeof(double);
-    const int64_t blocks = ceil_div(p->nwaves, kBatchWpb);
-    hipLaunchKernelGGL(batched_kernel, dim3((unsigned)blocks), dim3(64 * kBatchWpb), lds, s,
-                       reinterpret_cast<const BatchMat*>(b), reinterpret_cast<const int2*>(b + p->off_tiles),
-                       (int64_t)p->tiles.size(), p->nwaves, reinterpret_cast<double*>(b + p->off_slots), counters,
-                       queue, p->np_max);
-    return hipGetLastError() == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+    hipLaunchKernelGGL(batched_stage_kernel, dim3((unsigned)ceil_div(p->nwaves, kBatchWpb)), dim3(64 * kBatchWpb),
+                       lds, s, mats, reinterpret_cast<const int2*>(b + p->off_tiles), (int64_t)p->tiles.size(),
+                       p->nwaves, slots, p->np_max);
+    if (hipGetLastError() != hipSuccess) return QLESS_ERR_HIP;
+    const BatchGroup* groups = reinterpret_cast<const BatchGroup*>(b + p->off_groups);
+    int64_t lo = 0;
+    for (int64_t hi : p->level_end) {
+        const int64_t ng = hi - lo;
+        const int64_t nw = std::min<int64_t>(ng, (int64_t)p->waves_cap);
+        hipLaunchKernelGGL(batched_tree_kernel, dim3((unsigned)ceil_div(nw, kBatchWpb)), dim3(64 * kBatchWpb), lds, s,
+                           mats, groups + lo, ng, nw, slots, p->np_max);
+        if (hipGetLastError() != hipSuccess) return QLESS_ERR_HIP;
+        lo = hi;
+    }
+    return QLESS_OK;
 }
 
 size_t batch_plan_bytes(const qless_batch_plan* p) { return p ? p->bytes : 0; }

@@ -203,8 +203,8 @@ struct TsqrPlan {
     int64_t k0 = 0;            // stage-1 wavefronts (= stacked R blocks)
     int fan_in = 0;            // blocks combined per tree wavefront
     int levels = 0;            // tree levels (0: one wavefront writes R directly)
-    size_t counter_bytes = 0;  // group arrival counters of the tree
-    size_t slot_bytes = 0;     // stacked-triangle slots of every tree level
+    size_t ybytes_a = 0;       // stacked triangles of stage 1 (and of odd tree levels)
+    size_t ybytes_b = 0;       // stacked triangles of even tree levels
     size_t work_bytes = 0;     // total workspace
 };
 
@@ -258,8 +258,16 @@ hipError_t launch_copy_int(const int* src, int* dst, hipStream_t stream);
 struct BatchMat {
     const double* X;
     double* R;
-    int64_t m, ldx, ldr, tile_rows, slot_base, cnt_base;
+    int64_t m, ldx, ldr, tile_rows, slot_base;
     int n, np, accumulate, ntiles;
+};
+
+// One tree group of a batched call: fold the gsize stacked triangles at
+// slots + src into one, written at slots + dst, or (dst < 0, the root) into
+// the matrix's R.
+struct BatchGroup {
+    int64_t src, dst;
+    int mat, gsize;
 };
 
 // Batched TSQR (batched.hip).

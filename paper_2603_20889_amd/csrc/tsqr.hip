@@ -2,9 +2,6 @@
 // wavefront count, rows per wavefront, tree levels, workspace) and the
 // stage-1 + tree launch sequence.  The kernels are in tsqr_kernels.h and are
 // instantiated per padded column count in tsqr_i*.hip.
-#include <atomic>
-#include <chrono>
-
 #include "tsqr_kernels.h"
 
 namespace qless {
@@ -12,20 +9,19 @@ namespace qless {
 // Kernel instances (tsqr_i*.hip): launch_fold_np<NP>_r<RPL>.
 #define QLESS_DECL(NP, RPL)                                                                              \
     hipError_t launch_fold_np##NP##_r##RPL(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, \
-                                           int64_t nw, double* R, int64_t ldr, double* slots,           \
-                                           unsigned long long* counters, int fan_in,                    \
-                                           unsigned long long tag, hipStream_t s);
+                                           int64_t nw, double* Y, int64_t ldy, int64_t ystride,         \
+                                           int normalise, hipStream_t s);
 #define QLESS_INSTANCES(X)                                                                          \
     X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(10, 6) X(12, 5)          \
-    X(14, 4) X(16, 4) X(24, 16) X(32, 12) X(40, 10) X(48, 8) X(56, 7) X(64, 5)                      \
+    X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)                     \
     X(1, 32) X(2, 16) X(4, 8) X(8, 4) X(16, 2) X(32, 8) X(64, 4)
 QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
 
 namespace {
 
-typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, double*,
-                              unsigned long long*, int, unsigned long long, hipStream_t);
+typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, int64_t, int,
+                              hipStream_t);
 
 struct Instance {
     int npad;
@@ -88,23 +84,6 @@ int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rpl) {
     return QLESS_OK;
 }
 
-namespace {
-
-// Tags of successive calls (48 bits, never 0), starting from a value that
-// differs between processes, so that a workspace left over by an earlier
-// call or process never carries the current tag.
-unsigned long long next_call_tag() {
-    static std::atomic<unsigned long long> ctr{
-        (unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() * 0x9E3779B97F4A7C15ull};
-    unsigned long long t;
-    do {
-        t = ctr.fetch_add(1) & 0xFFFFFFFFFFFFull;
-    } while (t == 0);
-    return t;
-}
-
-}  // namespace
-
 TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     TsqrPlan p;
     const Tuning t = (n >= 1 && n <= QLESS_MAX_N) ? g_tuning[n] : Tuning{};
@@ -122,16 +101,13 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
     p.fan_in = t.fan_in ? t.fan_in : 16;
     int levels = 0;
-    int64_t slots = 0, counters = 0;
-    for (int64_t k = p.k0; k > 1; k = ceil_div(k, p.fan_in)) {
-        ++levels;
-        slots += k * n * n;
-        counters += ceil_div(k, p.fan_in);
-    }
+    for (int64_t k = p.k0; k > 1; k = ceil_div(k, p.fan_in)) ++levels;
     p.levels = levels;
-    p.counter_bytes = align_up((size_t)counters * sizeof(unsigned long long), 256);
-    p.slot_bytes = align_up((size_t)slots * sizeof(double), 256);
-    p.work_bytes = levels == 0 ? 256 : p.counter_bytes + p.slot_bytes;
+    // two stacked buffers used in turn: level l reads one and writes the other
+    const size_t blk = (size_t)n * (size_t)n * sizeof(double);
+    p.ybytes_a = align_up((size_t)p.k0 * blk, 256);
+    p.ybytes_b = align_up((size_t)ceil_div(p.k0, p.fan_in) * blk, 256);
+    p.work_bytes = levels == 0 ? 256 : p.ybytes_a + p.ybytes_b;
     return p;
 }
 
@@ -140,12 +116,35 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
     if (plan.levels > 0 && work == nullptr) return hipErrorInvalidValue;  // the tree needs its buffers
     const Instance* in = find_instance(plan.npad, plan.rows_per_lane);
     if (!in) return hipErrorInvalidValue;
-    unsigned long long* counters = static_cast<unsigned long long*>(work);
-    double* slots = reinterpret_cast<double*>(static_cast<char*>(work) + plan.counter_bytes);
+    const int ni = (int)n;
+    const int64_t nn = n * n;
+    hipError_t e;
     timing_begin(kTimeTsqrStage1, stream);
-    const hipError_t e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, R, ldr, plan.levels ? slots : nullptr,
-                                plan.levels ? counters : nullptr, plan.fan_in, next_call_tag(), stream);
+    if (plan.levels == 0) {
+        e = in->fn(X, m, ni, ldx, plan.rows_per_wave, 1, R, ldr, 0, 1, stream);
+        timing_end(kTimeTsqrStage1, stream);
+        return e;
+    }
+    double* src = static_cast<double*>(work);
+    double* dst = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
+    e = in->fn(X, m, ni, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, stream);
     timing_end(kTimeTsqrStage1, stream);
+    // tree (Alg. 2, second call, repeated): wavefront g of a level folds the
+    // fan_in triangles g*fan_in .. of the previous level, read as one tall
+    // (fan_in*n) x n matrix.
+    const int64_t rpw = (int64_t)plan.fan_in * n;
+    for (int64_t k = plan.k0; e == hipSuccess && k > 1;) {
+        const int64_t kn = ceil_div(k, plan.fan_in);
+        if (kn == 1) {
+            e = in->fn(src, k * n, ni, n, rpw, 1, R, ldr, 0, 1, stream);
+        } else {
+            e = in->fn(src, k * n, ni, n, rpw, kn, dst, n, nn, 0, stream);
+            double* t = src;
+            src = dst;
+            dst = t;
+        }
+        k = kn;
+    }
     return e;
 }
 

@@ -4,23 +4,19 @@
 
 namespace qless {
 hipError_t launch_fold_np1_r64(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<1, 64>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<1, 64>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 hipError_t launch_fold_np2_r32(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<2, 32>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<2, 32>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 hipError_t launch_fold_np3_r21(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<3, 21>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<3, 21>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 hipError_t launch_fold_np4_r16(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<4, 16>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<4, 16>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 }  // namespace qless

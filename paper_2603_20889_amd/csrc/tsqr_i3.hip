@@ -4,23 +4,19 @@
 
 namespace qless {
 hipError_t launch_fold_np10_r6(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<10, 6>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<10, 6>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 hipError_t launch_fold_np12_r5(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<12, 5>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<12, 5>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 hipError_t launch_fold_np14_r4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<14, 4>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<14, 4>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 hipError_t launch_fold_np16_r4(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<16, 4>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<16, 4>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 }  // namespace qless

@@ -3,9 +3,8 @@
 #include "tsqr_kernels.h"
 
 namespace qless {
-hipError_t launch_fold_np64_r5(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* R, int64_t ldr, double* slots, unsigned long long* counters,
-                               int fan_in, unsigned long long tag, hipStream_t s) {
-    return tsqr_detail::launch_fused<64, 5>(X, m, n, ldx, rpw, nw, R, ldr, slots, counters, fan_in, tag, s);
+hipError_t launch_fold_np64_r7(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<64, 7>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
 }  // namespace qless

@@ -1,29 +1,33 @@
 // Q-less Householder TSQR kernels for gfx950 (paper Alg. 2-4).
 //
-// Stage 1 (Alg. 2, first call; Alg. 3): the rows of X are split into k
-// contiguous blocks, one per wavefront.  A wavefront streams its block in
-// panels and keeps the running triangle R of the rows seen so far in LDS
-// (wavefront-private; broadcast reads, one-lane writes).  Each panel W is
-// folded in by the structured Householder QR of [R; W] (Alg. 4 without the
-// column pairing): the reflector of column j pivots on R_jj and spans column
-// j of W, so it touches only row j of R and the panel.  Q and the reflectors
-// are never stored.  At the end the wavefront writes its R_i (n x n) into
-// the stacked buffer Y.
+// One kernel, tsqr_fold_kernel, serves both stages of Alg. 2.  Its
+// wavefront w folds the rows [w*rows_per_wave, (w+1)*rows_per_wave) of a
+// row-major matrix into an n x n triangle and writes it out:
+//   stage 1: the rows of X, split into k contiguous blocks; the k triangles
+//            R_i go to a stacked buffer Y (k*n rows, n columns);
+//   tree   : the stacked buffer itself, fan_in triangles per wavefront,
+//            level after level until one wavefront remains; that one writes
+//            R with its diagonal made non-negative.
+// Every level is its own launch: the end of a launch is what makes the
+// triangles of one wavefront visible to the next level, so no wavefront
+// ever synchronises with another (an agent-scope fence per wavefront costs
+// an L2 write-back and invalidate on gfx950, which stalls the streaming of
+// every other wavefront on that XCD).
+//
+// A wavefront streams its rows in panels and keeps the running triangle R of
+// the rows seen so far in LDS (wavefront-private; broadcast reads, one-lane
+// writes).  Each panel W is folded in by the structured Householder QR of
+// [R; W] (Alg. 4 without the column pairing): the reflector of column j
+// pivots on R_jj and spans column j of W, so it touches only row j of R and
+// the panel.  Q and the reflectors are never stored.
 //
 // Two register layouts of a panel:
-//   n <= 16 (tsqr_fold_kernel): lane l holds RPL = 64/n full rows
-//     (l, l+64, ...), i.e. 64 doubles; the K = n - j dot products of step j
-//     are per-lane partial sums reduced over 64 lanes by one transposed
-//     butterfly (wave_sum_multi).
-//   n > 16 (tsqr_fold2d_kernel): 8 row groups x 8 column groups; lane
-//     (rg, cg) holds RPL rows of the columns cg, cg+8, ...; the pivot column
-//     is broadcast inside the row group and the sums run over the 8 row
-//     groups only.
-//
-// Stage 2 (Alg. 2, second call): the stacked triangles are reduced by a tree
-// of the same kernels -- each wavefront of a level treats fan_in consecutive
-// R_i as a tall (fan_in*n) x n matrix -- until one remains; the last launch
-// writes R with its diagonal made non-negative.
+//   n <= 16: lane l holds RPL full rows (l, l+64, ...), RPL * NP ~ 64
+//     doubles; the K = n - j dot products of step j are per-lane partial sums
+//     reduced over 64 lanes by one transposed butterfly.
+//   n > 16: 8 row groups x 8 column groups; lane (rg, cg) holds RPL rows of
+//     the columns cg, cg+8, ...; the pivot column is broadcast inside the row
+//     group and the sums run over the 8 row groups only.
 #pragma once
 
 #include "qless_internal.h"
@@ -78,16 +82,6 @@ __device__ __forceinline__ void reflector_scalars(double alpha, double s, double
 // partial dot products of column J with columns J..NP-1 in each lane, sums
 // all K over the wavefront in one transposed butterfly, and applies the
 // reflector; the scalars (norm, beta, gamma) are wave-uniform.
-// Prefetch of the next panel into registers whose columns are finished:
-// after step J the pivot column J (and every earlier one) is dead, so the
-// next panel's columns are loaded into them while the later steps run.
-struct PanelPrefetch {
-    bool on;                       // wave-uniform: the next panel is a full interior panel
-    __amdgpu_buffer_rsrc_t rs;     // resource rebased at the next panel
-    int vo;                        // lane offset (bytes)
-    int so;                        // row-stripe offset (bytes)
-};
-
 // Per-lane value index after the transposed butterfly: byte K-1 of the
 // packed words is red_origin(K, lane), the value whose wavefront total this
 // lane holds when K values are summed.
@@ -117,7 +111,7 @@ struct LaneOrigins {
 template <int NP, int RPL, int J>
 struct FoldStep {
     __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, double* __restrict__ Cw,
-                                               const LaneOrigins<NP>& org, int lane, const PanelPrefetch& pf) {
+                                               const LaneOrigins<NP>& org, int lane) {
         if constexpr (J < NP) {
             constexpr int K = NP - J;
             double p[K];
@@ -150,25 +144,7 @@ struct FoldStep {
                         for (int i = 0; i < RPL; ++i) x[i][J + t] = fma(-c[t], x[i][J], x[i][J + t]);
                 }
             }
-            if constexpr (J % 2 == 1) {
-                if (pf.on) {
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) {
-                        const f64x2 v2 = __builtin_bit_cast(
-                            f64x2, __builtin_amdgcn_raw_buffer_load_b128(pf.rs, pf.vo + (J - 1) * 8, pf.so * i, 0));
-                        x[i][J - 1] = v2[0];
-                        x[i][J] = v2[1];
-                    }
-                }
-            } else if constexpr (J == NP - 1) {
-                if (pf.on) {
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i)
-                        x[i][J] = __builtin_bit_cast(
-                            double, __builtin_amdgcn_raw_buffer_load_b64(pf.rs, pf.vo + J * 8, pf.so * i, 0));
-                }
-            }
-            FoldStep<NP, RPL, J + 1>::run(x, Rw, Cw, org, lane, pf);
+            FoldStep<NP, RPL, J + 1>::run(x, Rw, Cw, org, lane);
         }
     }
 };
@@ -220,9 +196,9 @@ __device__ __forceinline__ void load_panel_1d(double (&x)[RPL][NP], const double
 }
 
 // Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
-// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  While a
-// panel is folded, the next one (when it is a full interior panel) streams
-// into the registers of the columns already finished.
+// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  A panel
+// is loaded whole before it is folded: the chunks of one cache line are then
+// requested back to back, so the line is fetched once.
 template <int NP, int RPL>
 __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
                                              int64_t r_end, double* __restrict__ Rw, int lane) {
@@ -232,20 +208,10 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
     LaneOrigins<NP> org;
     org.init(lane);
     double* Cw = Rw + tri_size<NP>();   // per-wavefront coefficient exchange
-    double x[RPL][NP];
-    load_panel_1d<NP, RPL>(x, X, n, ldx, r_begin, r_end, fast, lane);
-    for (int64_t base = r_begin;;) {
-        const int64_t next = base + PANEL;
-        PanelPrefetch pf;
-        pf.on = fast && next + PANEL <= r_end;
-        pf.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + (pf.on ? next : 0) * ldx), (short)0,
-                                                  0x7FFFFFFF, 0x00020000);
-        pf.vo = lane * (int)(ldx * 8);
-        pf.so = (int)(ldx * 8 * kWave);
-        FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane, pf);
-        if (next >= r_end) break;
-        if (!pf.on) load_panel_1d<NP, RPL>(x, X, n, ldx, next, r_end, false, lane);
-        base = next;
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        double x[RPL][NP];
+        load_panel_1d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
+        FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
     }
 }
 
@@ -282,8 +248,7 @@ __device__ __forceinline__ double sum_over_row_groups(double v) {
 template <int NP, int RPL, int J>
 struct FoldStep2D {
     static constexpr int NC = NP / kG2;
-    __device__ static __forceinline__ void run(double (&x)[RPL][NP / kG2], double* __restrict__ Rw, int lane,
-                                               const PanelPrefetch& pf) {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP / kG2], double* __restrict__ Rw, int lane) {
         if constexpr (J < NP) {
             constexpr int cgJ = J % kG2;
             constexpr int uJ = J / kG2;
@@ -321,15 +286,7 @@ struct FoldStep2D {
                 }
                 if (lane == 0) Rw[tri_row<NP>(J)] = beta;
             }
-            if constexpr (J % kG2 == kG2 - 1) {   // slot uJ holds only finished columns now
-                if (pf.on) {
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i)
-                        x[i][uJ] = __builtin_bit_cast(
-                            double, __builtin_amdgcn_raw_buffer_load_b64(pf.rs, pf.vo, pf.so * i + kG2 * uJ * 8, 0));
-                }
-            }
-            FoldStep2D<NP, RPL, J + 1>::run(x, Rw, lane, pf);
+            FoldStep2D<NP, RPL, J + 1>::run(x, Rw, lane);
         }
     }
 };
@@ -373,21 +330,10 @@ __device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n
     constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
     if (r_begin >= r_end) return;
     const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
-    const int rg = lane / kG2, cg = lane % kG2;
-    double x[RPL][NC];
-    load_panel_2d<NP, RPL>(x, X, n, ldx, r_begin, r_end, fast, lane);
-    for (int64_t base = r_begin;;) {
-        const int64_t next = base + PANEL;
-        PanelPrefetch pf;
-        pf.on = fast && next + PANEL <= r_end;
-        pf.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + (pf.on ? next : 0) * ldx), (short)0,
-                                                  0x7FFFFFFF, 0x00020000);
-        pf.vo = (int)((rg * ldx + cg) * 8);
-        pf.so = (int)(kRG2 * ldx * 8);
-        FoldStep2D<NP, RPL, 0>::run(x, Rw, lane, pf);
-        if (next >= r_end) break;
-        if (!pf.on) load_panel_2d<NP, RPL>(x, X, n, ldx, next, r_end, false, lane);
-        base = next;
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        double x[RPL][NC];
+        load_panel_2d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
+        FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
     }
 }
 
@@ -427,41 +373,14 @@ __device__ __forceinline__ void store_r(const double* __restrict__ Rw, int n, do
     }
 }
 
-// Arrival at a tree group of `gsize` blocks.  The counter word holds
-// (tag << 16) | arrivals, where tag identifies the call: the first arriver
-// of a call finds a different tag (a previous call's, or an uninitialised
-// word) and restarts the count at 1, so the workspace needs no zeroing; the
-// last arriver clears the word, so a replay with the same tag (a captured
-// graph) also starts from zero.  Returns true in every lane of the
-// wavefront that completed the group.
-__device__ __forceinline__ bool tree_arrive(unsigned long long* word, unsigned long long tag, int gsize, int lane) {
-    int last = 0;
-    if (lane == 0) {
-        unsigned long long old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long nw;
-        while (true) {
-            nw = ((old >> 16) == tag) ? old + 1ull : ((tag << 16) | 1ull);
-            if (__hip_atomic_compare_exchange_strong(word, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT))
-                break;
-        }
-        last = ((nw & 0xFFFFull) == (unsigned long long)gsize) ? 1 : 0;
-        if (last) __hip_atomic_store(word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return __builtin_amdgcn_readfirstlane(last) != 0;
-}
-
-// The whole Q-less TSQR of one matrix in one launch (Alg. 2).
-//   Stage 1: wavefront w folds rows [w*rows_per_wave, ...) of X into R_w.
-//   Stage 2: R_w goes to its level-0 slot; the wavefront that completes a
-//   group of fan_in siblings folds the group's stacked triangles into the
-//   next level, and so on; the one completing the root writes R (ld ldr,
-//   non-negative diagonal).  No wavefront waits for another.
+// One launch of Alg. 2 (stage 1 or a tree level): wavefront w folds rows
+// [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle and
+// writes it at Y + w*ystride (leading dimension ldy); with normalise, rows of
+// a negative diagonal are negated (the final R).
 template <int NP, int RPL>
 __global__ void __launch_bounds__(64 * waves_per_block<NP>()) __attribute__((amdgpu_waves_per_eu(2)))
-tsqr_fused_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-                  int64_t nwaves, double* __restrict__ R, int64_t ldr, double* __restrict__ slots,
-                  unsigned long long* __restrict__ counters, int fan_in, unsigned long long tag) {
+tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int64_t ystride, int normalise) {
     constexpr int WPB = waves_per_block<NP>();
     __shared__ double Rsh[WPB][tri_size<NP>() + NP];
     const int lane = lane_id();
@@ -473,33 +392,16 @@ tsqr_fused_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, i
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
     fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
-    const int64_t nn = (int64_t)n * n;
-    int64_t count = nwaves, idx = w, sbase = 0, cbase = 0;
-    while (count > 1) {
-        store_r<NP>(Rw, n, slots + sbase + idx * nn, n, false, lane);
-        __threadfence();
-        const int64_t g = idx / fan_in;
-        const int gsize = (int)((count - g * fan_in < fan_in) ? count - g * fan_in : fan_in);
-        if (!tree_arrive(counters + cbase + g, tag, gsize, lane)) return;
-        __threadfence();
-        zero_r<NP>(Rw, lane);
-        fold_rows<NP, RPL>(slots + sbase + g * fan_in * nn, n, n, 0, (int64_t)gsize * n, Rw, lane);
-        sbase += count * nn;
-        cbase += ceil_div(count, fan_in);
-        idx = g;
-        count = ceil_div(count, fan_in);
-    }
-    store_r<NP>(Rw, n, R, ldr, true, lane);
+    store_r<NP>(Rw, n, Y + w * ystride, ldy, normalise != 0, lane);
 }
 
 template <int NP, int RPL>
-hipError_t launch_fused(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave, int64_t nwaves,
-                        double* R, int64_t ldr, double* slots, unsigned long long* counters, int fan_in,
-                        unsigned long long tag, hipStream_t stream) {
+hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave, int64_t nwaves,
+                       double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t stream) {
     constexpr int WPB = waves_per_block<NP>();
     const int64_t blocks = ceil_div(nwaves, WPB);
-    hipLaunchKernelGGL((tsqr_fused_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, X, m, n,
-                       ldx, rows_per_wave, nwaves, R, ldr, slots, counters, fan_in, tag);
+    hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, X, m, n, ldx,
+                       rows_per_wave, nwaves, Y, ldy, ystride, normalise);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
-"""GPU parity of the batched Q-less TSQR (one persistent launch for many
-matrices of uneven m and n) against the CPU oracle, plus its replay, graph
-capture and running-R (accumulate) behaviour."""
+"""GPU parity of the batched Q-less TSQR (one persistent stage-1 launch plus
+one launch per tree level for many matrices of uneven m and n) against the CPU
+oracle, plus its replay, graph capture and running-R (accumulate) behaviour."""
 import numpy as np
 import pytest
 import torch
@@ -33,7 +33,7 @@ def test_batched_matches_oracle(gpu):
         assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) >= 0.0)
         assert oracle.rel_err_r(R, Ro) <= 1e-12, X.shape
         assert oracle.gram_residual(X, R) <= 1e-13, X.shape
-    # replay: counters reset by the kernel itself -> bitwise identical
+    # replay: no state survives a call -> bitwise identical
     first = [R.clone() for R in Rs]
     plan.run()
     torch.cuda.synchronize(gpu)
