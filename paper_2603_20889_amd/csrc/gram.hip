@@ -135,7 +135,8 @@ gram_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
     for (int64_t base = r_begin; base < r_end; base += PANEL) {
         double x[RPL][NP];
-        tsqr_detail::load_panel_1d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
+        if (fast && base + PANEL <= r_end) tsqr_detail::load_panel_1d_fast<NP, RPL>(x, X, ldx, base, lane);
+        else tsqr_detail::load_panel_1d_tail<NP, RPL>(x, X, n, ldx, base, r_end, lane);
         if (HAS_M) {
             // y = x M for the lane's RPL rows, one column of M at a time so that
             // each M entry is read once from LDS and used for every row

@@ -14,7 +14,7 @@ namespace qless {
 #define QLESS_INSTANCES(X)                                                                          \
     X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(10, 6) X(12, 5)          \
     X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)                     \
-    X(1, 32) X(2, 16) X(4, 8) X(8, 4) X(16, 2) X(32, 8) X(64, 4)
+    X(1, 32) X(2, 16) X(4, 8) X(8, 4) X(16, 2) X(32, 8) X(64, 4) X(8, 5) X(16, 3)
 QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
 

@@ -31,4 +31,12 @@ hipError_t launch_fold_np64_r4(const double* X, int64_t m, int n, int64_t ldx, i
                                double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
     return tsqr_detail::launch_fold<64, 4>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
 }
+hipError_t launch_fold_np8_r5(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<8, 5>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
+}
+hipError_t launch_fold_np16_r3(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
+                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
+    return tsqr_detail::launch_fold<16, 3>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
+}
 }  // namespace qless

@@ -149,69 +149,208 @@ struct FoldStep {
     }
 };
 
+// Lane-private fold (n <= 8): lane l keeps its own running triangle Rl of
+// the rows it has loaded (packed, in registers) and folds its RPL rows of a
+// panel into it with no cross-lane traffic at all -- the reflector scalars
+// and coefficients are per lane, so one instruction serves 64 independent
+// folds.  The 64 triangles are combined once at the end (fold_lane_triangles).
+// Any partition of the rows gives a valid TSQR tree (Alg. 2), so this only
+// changes the order in which rows meet, not what is computed.
+template <int NP, int RPL, int J>
+struct LaneFoldStep {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double (&Rl)[NP * (NP + 1) / 2]) {
+        if constexpr (J < NP) {
+            constexpr int K = NP - J;
+            constexpr int r0 = tri_row<NP>(J);
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) s = fma(x[i][J], x[i][J], s);
+            const double alpha = Rl[r0];
+            double beta, u0, gamma;
+            reflector_scalars(alpha, s, beta, u0, gamma);
+            const bool nz = s != 0.0;          // a zero column is left as it is
+            gamma = nz ? gamma : 0.0;
+            u0 = nz ? u0 : 0.0;
+            Rl[r0] = nz ? beta : alpha;
+#pragma unroll
+            for (int t = 1; t < K; ++t) {
+                double d = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) d = fma(x[i][J], x[i][J + t], d);
+                const double coef = gamma * fma(u0, Rl[r0 + t], d);   // gamma * (u^T column J+t)
+                Rl[r0 + t] = fma(-coef, u0, Rl[r0 + t]);
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) x[i][J + t] = fma(-coef, x[i][J], x[i][J + t]);
+            }
+            LaneFoldStep<NP, RPL, J + 1>::run(x, Rl);
+        }
+    }
+};
+
+template <int NP>
+constexpr bool lane_private() {
+    return NP <= 8;
+}
+
 template <int NP>
 constexpr int waves_per_block() {
     return ((tri_size<NP>() + NP) * 8 * 4 <= 65536) ? 4 : 2;
 }
 
-// Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
-// ldx) into the wavefront's R, panel by panel (layout for n <= 16).
+// Panel loads for the layout of n <= 16: lane l gets rows base + l + 64 i
+// (i < RPL) into x[i][0..NP-1].
+//
+// Interior panel (all rows present, n == NP): buffer loads from a resource
+// rebased at the panel, lane offset in a VGPR, row-stripe offset in an SGPR;
+// the 16-byte chunks of one row are requested back to back, so a cache line
+// is fetched once.
 template <int NP, int RPL>
-__device__ __forceinline__ void load_panel_1d(double (&x)[RPL][NP], const double* __restrict__ X, int n, int64_t ldx,
-                                              int64_t base, int64_t r_end, bool fast, int lane) {
-    constexpr int64_t PANEL = (int64_t)kWave * RPL;
-    if (fast && base + PANEL <= r_end) {
-        // interior panel: buffer loads from a resource rebased at the panel,
-        // lane offset in a VGPR, row-stripe offset in an SGPR.
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
-        const int vo = lane * (int)(ldx * 8);
-        const int so = (int)(ldx * 8 * kWave);
+__device__ __forceinline__ void load_panel_1d_fast(double (&x)[RPL][NP], const double* __restrict__ X, int64_t ldx,
+                                                   int64_t base, int lane) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+    const int vo = lane * (int)(ldx * 8);
+    const int so = (int)(ldx * 8 * kWave);
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
+    for (int i = 0; i < RPL; ++i) {
 #pragma unroll
-            for (int c = 0; c < NP; c += 2) {
-                if (c + 1 < NP) {
-                    const f64x2 v =
-                        __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + c * 8, so * i, 0));
-                    x[i][c] = v[0];
-                    x[i][c + 1] = v[1];
-                } else {
-                    x[i][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + c * 8, so * i, 0));
-                }
+        for (int c = 0; c < NP; c += 2) {
+            if (c + 1 < NP) {
+                const f64x2 v =
+                    __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + c * 8, so * i, 0));
+                x[i][c] = v[0];
+                x[i][c + 1] = v[1];
+            } else {
+                x[i][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + c * 8, so * i, 0));
             }
-        }
-    } else {
-        // tail panel or padded width: guarded loads, zero fill
-        const int64_t left = r_end - base - lane;   // rows of this lane's stripe still in range
-        const double* x0 = X + (left > 0 ? base + lane : 0) * ldx;
-        const int64_t step = (int64_t)kWave * ldx;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const bool ok = (int64_t)kWave * i < left;
-#pragma unroll
-            for (int c = 0; c < NP; ++c) x[i][c] = (ok && c < n) ? x0[step * i + c] : 0.0;
         }
     }
 }
 
+// Tail panel or padded width: guarded loads, zero fill.
+template <int NP, int RPL>
+__device__ __forceinline__ void load_panel_1d_tail(double (&x)[RPL][NP], const double* __restrict__ X, int n,
+                                                   int64_t ldx, int64_t base, int64_t r_end, int lane) {
+    const int64_t left = r_end - base - lane;   // rows of this lane's stripe still in range
+    const double* x0 = X + (left > 0 ? base + lane : 0) * ldx;
+    const int64_t step = (int64_t)kWave * ldx;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const bool ok = (int64_t)kWave * i < left;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) x[i][c] = (ok && c < n) ? x0[step * i + c] : 0.0;
+    }
+}
+
+// Double buffering pays when two panels fit the registers next to the fold's
+// temporaries: the next panel is then in flight while the current one is
+// folded.
+template <int NP, int RPL>
+constexpr bool double_buffered() {
+    return RPL * NP <= 40;
+}
+
 // Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
-// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  A panel
-// is loaded whole before it is folded: the chunks of one cache line are then
-// requested back to back, so the line is fetched once.
+// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  Interior
+// panels come first; with double buffering the loads of panel p+1 are issued
+// before panel p is folded (the last interior panel is requested twice, so
+// every iteration issues the same loads and the wait before a fold only
+// covers the older panel).  The partial panel at the end, if any, follows.
+// Full panels [base, base + nfull*PANEL) with lane-private triangles; the
+// 64 triangles, stacked, are then folded into the wavefront's R by one
+// cross-lane pass with NP rows per lane.
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_panels_lane_private(const double* __restrict__ X, int64_t ldx, int64_t base,
+                                                         int64_t nfull, double* __restrict__ Rw,
+                                                         double* __restrict__ Cw, const LaneOrigins<NP>& org,
+                                                         int lane) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    double Rl[tri_size<NP>()];
+#pragma unroll
+    for (int e = 0; e < tri_size<NP>(); ++e) Rl[e] = 0.0;
+    double xa[RPL][NP];
+    if constexpr (double_buffered<NP, RPL>()) {
+        double xb[RPL][NP];
+        const int64_t last = base + (nfull - 1) * PANEL;
+        load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
+        while (true) {
+            load_panel_1d_fast<NP, RPL>(xb, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
+            LaneFoldStep<NP, RPL, 0>::run(xa, Rl);
+            base += PANEL;
+            if (base > last) break;
+            load_panel_1d_fast<NP, RPL>(xa, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
+            LaneFoldStep<NP, RPL, 0>::run(xb, Rl);
+            base += PANEL;
+            if (base > last) break;
+        }
+    } else {
+        for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+            load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
+            LaneFoldStep<NP, RPL, 0>::run(xa, Rl);
+        }
+    }
+    double xe[NP][NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) xe[i][c] = (c >= i) ? Rl[tri_row<NP>(i) + c - i] : 0.0;
+    FoldStep<NP, NP, 0>::run(xe, Rw, Cw, org, lane);
+}
+
+// Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
+// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  Interior
+// panels come first: for n <= 8 and at least kLanePrivateMin of them, with
+// lane-private triangles; otherwise with the cross-lane fold, double-buffered
+// when two panels fit (the loads of panel p+1 are issued before panel p is
+// folded; the last interior panel is requested twice, so every iteration
+// issues the same loads and the wait before a fold only covers the older
+// panel).  The partial panel at the end, if any, follows.
+constexpr int64_t kLanePrivateMin = 4;
+
 template <int NP, int RPL>
 __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
                                              int64_t r_end, double* __restrict__ Rw, int lane) {
     constexpr int64_t PANEL = (int64_t)kWave * RPL;
     if (r_begin >= r_end) return;
     const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
+    int64_t nfull = fast ? (r_end - r_begin) / PANEL : 0;
     LaneOrigins<NP> org;
     org.init(lane);
     double* Cw = Rw + tri_size<NP>();   // per-wavefront coefficient exchange
-    for (int64_t base = r_begin; base < r_end; base += PANEL) {
-        double x[RPL][NP];
-        load_panel_1d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
-        FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
+    double xa[RPL][NP];
+    int64_t base = r_begin;
+    if constexpr (lane_private<NP>()) {
+        if (nfull >= kLanePrivateMin) {
+            fold_panels_lane_private<NP, RPL>(X, ldx, base, nfull, Rw, Cw, org, lane);
+            base += nfull * PANEL;
+            nfull = 0;
+        }
+    }
+    if (nfull > 0) {
+        if constexpr (double_buffered<NP, RPL>()) {
+            double xb[RPL][NP];
+            const int64_t last = r_begin + (nfull - 1) * PANEL;
+            load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
+            while (true) {
+                load_panel_1d_fast<NP, RPL>(xb, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
+                FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
+                base += PANEL;
+                if (base > last) break;
+                load_panel_1d_fast<NP, RPL>(xa, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
+                FoldStep<NP, RPL, 0>::run(xb, Rw, Cw, org, lane);
+                base += PANEL;
+                if (base > last) break;
+            }
+        } else {
+            for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+                load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
+                FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
+            }
+        }
+    }
+    for (; base < r_end; base += PANEL) {
+        load_panel_1d_tail<NP, RPL>(xa, X, n, ldx, base, r_end, lane);
+        FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
     }
 }
 
