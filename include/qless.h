@@ -139,7 +139,8 @@ int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
  * Launch parameters of qless_tsqr_r for column count n, as chosen by an
  * autotuner: waves_per_cu = stage-1 wavefronts per compute unit (row blocks
  * k = CUs * waves_per_cu; 0 = default 8, at most 32), fan_in = blocks combined
- * per tree wavefront (0 = default 16, 2..256), rows_per_lane = panel rows
+ * per tree wavefront (0 = default: one panel of stacked rows for n <= 16,
+ * else 16; explicit values 2..256), rows_per_lane = panel rows
  * per lane, one of the compiled variants for that n (0 = default;
  * QLESS_ERR_UNSUPPORTED if no such variant).  Process-wide, not thread-safe;
  * query qless_workspace_bytes after changing it.  qless_tune_get returns the

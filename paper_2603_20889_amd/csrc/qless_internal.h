@@ -200,9 +200,13 @@ struct TsqrPlan {
     int npad = 0;              // padded column count of the kernel instance
     int rows_per_lane = 0;     // panel rows per lane (panel = 64 * rows_per_lane rows)
     int64_t rows_per_wave = 0; // stage-1 rows per wavefront
-    int64_t k0 = 0;            // stage-1 wavefronts (= stacked R blocks)
+    int64_t k0 = 0;            // stage-1 wavefronts
+    int wpb = 0;               // wavefronts per workgroup (one triangle per workgroup)
+    int64_t k1 = 0;            // stage-1 triangles (workgroups)
     int fan_in = 0;            // blocks combined per tree wavefront
-    int levels = 0;            // tree levels (0: one wavefront writes R directly)
+    int levels = 0;            // tree launches (0: stage 1 writes R directly)
+    bool block_tree = false;   // the last level is one workgroup (n <= 16)
+    int64_t tree_rows = 0;     // stacked rows per wavefront of that last level
     size_t ybytes_a = 0;       // stacked triangles of stage 1 (and of odd tree levels)
     size_t ybytes_b = 0;       // stacked triangles of even tree levels
     size_t work_bytes = 0;     // total workspace

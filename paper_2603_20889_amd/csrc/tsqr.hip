@@ -2,9 +2,12 @@
 // wavefront count, rows per wavefront, tree levels, workspace) and the
 // stage-1 + tree launch sequence.  The kernels are in tsqr_kernels.h and are
 // instantiated per padded column count in tsqr_i*.hip.
+#include <algorithm>
+
 #include "tsqr_kernels.h"
 
 namespace qless {
+
 
 // Kernel instances (tsqr_i*.hip): launch_fold_np<NP>_r<RPL>.
 #define QLESS_DECL(NP, RPL)                                                                              \
@@ -12,28 +15,67 @@ namespace qless {
                                            int64_t nw, double* Y, int64_t ldy, int64_t ystride,         \
                                            int normalise, hipStream_t s);
 #define QLESS_INSTANCES(X)                                                                          \
-    X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(10, 6) X(12, 5)          \
+    X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5)              \
     X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)                     \
-    X(1, 32) X(2, 16) X(4, 8) X(8, 4) X(16, 2) X(32, 8) X(64, 4) X(8, 5) X(16, 3)
+    X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(16, 2) X(32, 8) X(64, 4)  \
+    X(16, 3)
 QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
+// One-workgroup last tree level, compiled for n <= 16 (launch_tree_np<NP>_r<RPL>).
+#define QLESS_TREE_DECL(NP, RPL)                                                                            \
+    hipError_t launch_tree_np##NP##_r##RPL(const double* Y, int64_t k, int n, double* stage, double* R,     \
+                                           int64_t ldr, hipStream_t s);
+#define QLESS_TREE_INSTANCES(X)                                                                         \
+    X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5) X(14, 4)      \
+    X(16, 4) X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(16, 2) X(16, 3)
+QLESS_TREE_INSTANCES(QLESS_TREE_DECL)
+#undef QLESS_TREE_DECL
 
 namespace {
 
 typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, int64_t, int,
                               hipStream_t);
+typedef hipError_t (*TreeFn)(const double*, int64_t, int, double*, double*, int64_t, hipStream_t);
 
 struct Instance {
     int npad;
     int rpl;
     FoldFn fn;
+    TreeFn tree;   // one-workgroup last level (n <= 16), else null
 };
 
 const Instance kInstances[] = {
-#define QLESS_ENTRY(NP, RPL) {NP, RPL, launch_fold_np##NP##_r##RPL},
+#define QLESS_ENTRY(NP, RPL) {NP, RPL, launch_fold_np##NP##_r##RPL, nullptr},
     QLESS_INSTANCES(QLESS_ENTRY)
 #undef QLESS_ENTRY
 };
+
+struct TreeEntry {
+    int npad;
+    int rpl;
+    TreeFn fn;
+};
+
+const TreeEntry kTrees[] = {
+#define QLESS_TREE_ENTRY(NP, RPL) {NP, RPL, launch_tree_np##NP##_r##RPL},
+    QLESS_TREE_INSTANCES(QLESS_TREE_ENTRY)
+#undef QLESS_TREE_ENTRY
+};
+
+// Wavefronts per workgroup of the fold kernel (tsqr_detail::waves_per_block).
+constexpr int waves_per_block_for(int np) {
+    return ((np * (np + 1) / 2 + np) * 8 * 4 <= 65536) ? 4 : 2;
+}
+static_assert(waves_per_block_for(8) == tsqr_detail::waves_per_block<8>() &&
+                  waves_per_block_for(56) == tsqr_detail::waves_per_block<56>() &&
+                  waves_per_block_for(64) == tsqr_detail::waves_per_block<64>(),
+              "host and device workgroup sizes differ");
+
+TreeFn find_tree(int np, int rpl) {
+    for (const TreeEntry& t : kTrees)
+        if (t.npad == np && t.rpl == rpl) return t.fn;
+    return nullptr;
+}
 
 int npad_for(int64_t n) {
     static const int pads[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 24, 32, 40, 48, 56, 64};
@@ -79,7 +121,7 @@ int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rpl) {
     const Tuning& t = g_tuning[n];
     const Instance* in = find_instance(npad_for(n), t.rpl);
     if (waves_per_cu) *waves_per_cu = t.waves_per_cu ? t.waves_per_cu : 8;
-    if (fan_in) *fan_in = t.fan_in ? t.fan_in : 16;
+    if (fan_in) *fan_in = make_tsqr_plan(1, n, 1).fan_in;
     if (rpl) *rpl = in->rpl;
     return QLESS_OK;
 }
@@ -99,14 +141,29 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     if (m <= 4 * panel) rpw = ceil_div(m > 0 ? m : 1, panel) * panel;
     p.rows_per_wave = rpw;
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
-    p.fan_in = t.fan_in ? t.fan_in : 16;
+    p.wpb = waves_per_block_for(in->npad);
+    // Each launch leaves one triangle per workgroup.  Tree for n <= 16:
+    // fan-in levels of one panel per wavefront (fan_in = panel / n) until the
+    // remaining triangles fit one panel per wavefront of the one-workgroup
+    // last level, which then writes R.  Wider n: fan-in 16 levels throughout.
+    p.block_tree = find_tree(in->npad, in->rpl) != nullptr;
+    p.tree_rows = p.block_tree ? panel : 0;
+    p.fan_in = t.fan_in ? t.fan_in : (p.block_tree ? (int)std::max<int64_t>(2, panel / n) : 16);
+    p.k1 = ceil_div(p.k0, p.wpb);
     int levels = 0;
-    for (int64_t k = p.k0; k > 1; k = ceil_div(k, p.fan_in)) ++levels;
+    int64_t k = p.k1;
+    while (k > 1) {
+        ++levels;
+        if (p.block_tree && k * n <= (int64_t)tsqr_detail::kTreeWaves * p.tree_rows) break;
+        k = ceil_div(ceil_div(k, p.fan_in), p.wpb);
+    }
     p.levels = levels;
     // two stacked buffers used in turn: level l reads one and writes the other
+    // (the last level's per-wavefront triangles go to the buffer not read)
     const size_t blk = (size_t)n * (size_t)n * sizeof(double);
-    p.ybytes_a = align_up((size_t)p.k0 * blk, 256);
-    p.ybytes_b = align_up((size_t)ceil_div(p.k0, p.fan_in) * blk, 256);
+    const size_t ybytes = align_up((size_t)std::max<int64_t>(p.k1, tsqr_detail::kTreeWaves) * blk, 256);
+    p.ybytes_a = ybytes;
+    p.ybytes_b = ybytes;
     p.work_bytes = levels == 0 ? 256 : p.ybytes_a + p.ybytes_b;
     return p;
 }
@@ -120,8 +177,8 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
     const int64_t nn = n * n;
     hipError_t e;
     timing_begin(kTimeTsqrStage1, stream);
-    if (plan.levels == 0) {
-        e = in->fn(X, m, ni, ldx, plan.rows_per_wave, 1, R, ldr, 0, 1, stream);
+    if (plan.k1 == 1) {
+        e = in->fn(X, m, ni, ldx, plan.rows_per_wave, plan.k0, R, ldr, 0, 1, stream);
         timing_end(kTimeTsqrStage1, stream);
         return e;
     }
@@ -131,14 +188,21 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
     timing_end(kTimeTsqrStage1, stream);
     // tree (Alg. 2, second call, repeated): wavefront g of a level folds the
     // fan_in triangles g*fan_in .. of the previous level, read as one tall
-    // (fan_in*n) x n matrix.
+    // (fan_in*n) x n matrix, and each workgroup leaves one triangle.
     const int64_t rpw = (int64_t)plan.fan_in * n;
-    for (int64_t k = plan.k0; e == hipSuccess && k > 1;) {
-        const int64_t kn = ceil_div(k, plan.fan_in);
+    TreeFn tree = plan.block_tree ? find_tree(plan.npad, plan.rows_per_lane) : nullptr;
+    int64_t k = plan.k1;
+    while (e == hipSuccess && k > 1) {
+        if (tree && k * n <= (int64_t)tsqr_detail::kTreeWaves * plan.tree_rows) {
+            e = tree(src, k, ni, dst, R, ldr, stream);
+            break;
+        }
+        const int64_t nw = ceil_div(k, plan.fan_in);
+        const int64_t kn = ceil_div(nw, plan.wpb);
         if (kn == 1) {
-            e = in->fn(src, k * n, ni, n, rpw, 1, R, ldr, 0, 1, stream);
+            e = in->fn(src, k * n, ni, n, rpw, nw, R, ldr, 0, 1, stream);
         } else {
-            e = in->fn(src, k * n, ni, n, rpw, kn, dst, n, nn, 0, stream);
+            e = in->fn(src, k * n, ni, n, rpw, nw, dst, n, nn, 0, stream);
             double* t = src;
             src = dst;
             dst = t;

@@ -2,14 +2,16 @@
 //
 // One kernel, tsqr_fold_kernel, serves both stages of Alg. 2.  Its
 // wavefront w folds the rows [w*rows_per_wave, (w+1)*rows_per_wave) of a
-// row-major matrix into an n x n triangle and writes it out:
-//   stage 1: the rows of X, split into k contiguous blocks; the k triangles
-//            R_i go to a stacked buffer Y (k*n rows, n columns);
+// row-major matrix into an n x n triangle; the wavefronts of a workgroup
+// combine theirs in LDS and the workgroup writes one triangle:
+//   stage 1: the rows of X, split into k contiguous blocks; the triangles go
+//            to a stacked buffer Y (rows of triangles, n columns);
 //   tree   : the stacked buffer itself, fan_in triangles per wavefront,
-//            level after level until one wavefront remains; that one writes
-//            R with its diagonal made non-negative.
+//            level after level until one workgroup remains; that one writes
+//            R with its diagonal made non-negative (for n <= 16 the last
+//            level is tsqr_tree_block_kernel).
 // Every level is its own launch: the end of a launch is what makes the
-// triangles of one wavefront visible to the next level, so no wavefront
+// triangles of one workgroup visible to the next level, so no workgroup
 // ever synchronises with another (an agent-scope fence per wavefront costs
 // an L2 write-back and invalidate on gfx950, which stalls the streaming of
 // every other wavefront on that XCD).
@@ -21,10 +23,13 @@
 // pivots on R_jj and spans column j of W, so it touches only row j of R and
 // the panel.  Q and the reflectors are never stored.
 //
-// Two register layouts of a panel:
-//   n <= 16: lane l holds RPL full rows (l, l+64, ...), RPL * NP ~ 64
-//     doubles; the K = n - j dot products of step j are per-lane partial sums
-//     reduced over 64 lanes by one transposed butterfly.
+// Register layouts of a panel:
+//   n <= 16: lane l holds RPL full rows (l, l+64, ...); the K = n - j dot
+//     products of step j are per-lane partial sums reduced over 64 lanes by
+//     one transposed butterfly.  For n <= 8 the interior panels are instead
+//     folded lane-privately (each lane its own triangle, no cross-lane
+//     traffic) and, for contiguous rows, streamed through LDS with
+//     direct-to-LDS nontemporal loads.
 //   n > 16: 8 row groups x 8 column groups; lane (rg, cg) holds RPL rows of
 //     the columns cg, cg+8, ...; the pivot column is broadcast inside the row
 //     group and the sums run over the 8 row groups only.
@@ -250,12 +255,6 @@ constexpr bool double_buffered() {
     return RPL * NP <= 40;
 }
 
-// Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
-// ldx) into the wavefront's R, panel by panel (layout for n <= 16).  Interior
-// panels come first; with double buffering the loads of panel p+1 are issued
-// before panel p is folded (the last interior panel is requested twice, so
-// every iteration issues the same loads and the wait before a fold only
-// covers the older panel).  The partial panel at the end, if any, follows.
 // Full panels [base, base + nfull*PANEL) with lane-private triangles; the
 // 64 triangles, stacked, are then folded into the wavefront's R by one
 // cross-lane pass with NP rows per lane.
@@ -297,6 +296,82 @@ __device__ __forceinline__ void fold_panels_lane_private(const double* __restric
     FoldStep<NP, NP, 0>::run(xe, Rw, Cw, org, lane);
 }
 
+// Staged lane-private fold: for contiguous rows (ldx == n == NP) the panels
+// stream through a wavefront-private LDS buffer with direct-to-LDS,
+// nontemporal buffer loads (buffer_load_dwordx4 ... nt lds): every load
+// instruction moves 1 KB of consecutive bytes, so each cache line is fetched
+// by one instruction and nothing is kept in the caches.  The next panel is in
+// flight while the current one, read from LDS into registers in the row
+// layout, is folded.  Waits are explicit (s_waitcnt with a compiler memory
+// barrier): the loads of panel p are complete before it is read from LDS,
+// and the reads are complete before panel p+1 overwrites the buffer.
+template <int NP, int RPL>
+constexpr bool staged_instance() {
+    return lane_private<NP>() && double_buffered<NP, RPL>() && (RPL * NP) % 2 == 0;
+}
+
+__device__ __forceinline__ void wait_memory() {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+}
+
+constexpr int kNontemporal = 2;   // buffer cache policy: nt
+
+template <int NP, int RPL>
+__device__ __forceinline__ void stage_panel(const double* __restrict__ X, int64_t base, double* stage, int lane) {
+    constexpr int NCHUNK = RPL * NP / 2;   // 1 KB chunks: 64 lanes x 16 bytes
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * NP), (short)0, 0x7FFFFFFF, 0x00020000);
+#pragma unroll
+    for (int j = 0; j < NCHUNK; ++j)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(stage + j * 128), 16,
+                                                 lane * 16, j * 1024, 0, kNontemporal);
+}
+
+template <int NP, int RPL>
+__device__ __forceinline__ void read_staged_panel(double (&x)[RPL][NP], const double* stage, int lane) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const double* row = stage + (lane + kWave * i) * NP;
+#pragma unroll
+        for (int c = 0; c < NP; c += 2) {
+            if constexpr (NP % 2 == 0) {
+                const f64x2 v = *reinterpret_cast<const f64x2*>(row + c);
+                x[i][c] = v[0];
+                x[i][c + 1] = v[1];
+            } else {
+                x[i][c] = row[c];
+                if (c + 1 < NP) x[i][c + 1] = row[c + 1];
+            }
+        }
+    }
+}
+
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_panels_lane_private_staged(const double* __restrict__ X, int64_t base,
+                                                                int64_t nfull, double* __restrict__ Rw,
+                                                                double* __restrict__ Cw, const LaneOrigins<NP>& org,
+                                                                int lane, double* stage) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    double Rl[tri_size<NP>()];
+#pragma unroll
+    for (int e = 0; e < tri_size<NP>(); ++e) Rl[e] = 0.0;
+    stage_panel<NP, RPL>(X, base, stage, lane);
+    for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+        double x[RPL][NP];
+        wait_memory();                       // panel p is in LDS
+        read_staged_panel<NP, RPL>(x, stage, lane);
+        wait_memory();                       // and in registers: the buffer is free
+        if (p + 1 < nfull) stage_panel<NP, RPL>(X, base + PANEL, stage, lane);
+        LaneFoldStep<NP, RPL, 0>::run(x, Rl);
+    }
+    double xe[NP][NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) xe[i][c] = (c >= i) ? Rl[tri_row<NP>(i) + c - i] : 0.0;
+    FoldStep<NP, NP, 0>::run(xe, Rw, Cw, org, lane);
+}
+
 // Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
 // ldx) into the wavefront's R, panel by panel (layout for n <= 16).  Interior
 // panels come first: for n <= 8 and at least kLanePrivateMin of them, with
@@ -309,7 +384,8 @@ constexpr int64_t kLanePrivateMin = 4;
 
 template <int NP, int RPL>
 __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
-                                             int64_t r_end, double* __restrict__ Rw, int lane) {
+                                             int64_t r_end, double* __restrict__ Rw, int lane,
+                                             double* stage = nullptr) {
     constexpr int64_t PANEL = (int64_t)kWave * RPL;
     if (r_begin >= r_end) return;
     const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
@@ -321,7 +397,14 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
     int64_t base = r_begin;
     if constexpr (lane_private<NP>()) {
         if (nfull >= kLanePrivateMin) {
-            fold_panels_lane_private<NP, RPL>(X, ldx, base, nfull, Rw, Cw, org, lane);
+            if constexpr (staged_instance<NP, RPL>()) {
+                if (stage != nullptr && ldx == NP)
+                    fold_panels_lane_private_staged<NP, RPL>(X, base, nfull, Rw, Cw, org, lane, stage);
+                else
+                    fold_panels_lane_private<NP, RPL>(X, ldx, base, nfull, Rw, Cw, org, lane);
+            } else {
+                fold_panels_lane_private<NP, RPL>(X, ldx, base, nfull, Rw, Cw, org, lane);
+            }
             base += nfull * PANEL;
             nfull = 0;
         }
@@ -478,8 +561,9 @@ __device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n
 
 template <int NP, int RPL>
 __device__ __forceinline__ void fold_rows(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
-                                          int64_t r_end, double* __restrict__ Rw, int lane) {
-    if constexpr (NP <= 16) fold_rows_1d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
+                                          int64_t r_end, double* __restrict__ Rw, int lane,
+                                          double* stage = nullptr) {
+    if constexpr (NP <= 16) fold_rows_1d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane, stage);
     else fold_rows_2d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
 }
 
@@ -512,26 +596,88 @@ __device__ __forceinline__ void store_r(const double* __restrict__ Rw, int n, do
     }
 }
 
+// Fold the packed triangles that wavefronts 1..count-1 of the workgroup left
+// in LDS (regions Rsh0 + w*stride) into wavefront 0's (region 0, which thus
+// accumulates R([R_0; R_1; ...])): their rows, stacked, form a
+// (count-1)*n x n matrix, folded panel by panel in the caller's register
+// layout.  The order is fixed, so the result does not depend on which
+// wavefront runs it.
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, int stride, int count, int n,
+                                                     int lane) {
+    double* __restrict__ Rw = Rsh0;
+    const int rows = (count - 1) * n;
+    auto value = [&](int r, int c) -> double {
+        if (r >= rows || c >= n) return 0.0;
+        const int t = r / n, i = r - t * n;
+        if (c < i) return 0.0;
+        return Rsh0[(t + 1) * stride + tri_row<NP>(i) + c - i];
+    };
+    if constexpr (NP <= 16) {
+        LaneOrigins<NP> org;
+        org.init(lane);
+        double* Cw = Rw + tri_size<NP>();
+        for (int base = 0; base < rows; base += kWave * RPL) {
+            double x[RPL][NP];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+#pragma unroll
+                for (int c = 0; c < NP; ++c) x[i][c] = value(base + lane + kWave * i, c);
+            FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
+        }
+    } else {
+        const int rg = lane / kG2, cg = lane % kG2;
+        for (int base = 0; base < rows; base += kRG2 * RPL) {
+            double x[RPL][NP / kG2];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+#pragma unroll
+                for (int u = 0; u < NP / kG2; ++u) x[i][u] = value(base + rg + kRG2 * i, cg + kG2 * u);
+            FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
+        }
+    }
+}
+
 // One launch of Alg. 2 (stage 1 or a tree level): wavefront w folds rows
-// [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle and
-// writes it at Y + w*ystride (leading dimension ldy); with normalise, rows of
-// a negative diagonal are negated (the final R).
+// [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle; the
+// last wavefront of each workgroup to finish folds the triangles of
+// wavefronts 1.. into wavefront 0's, in that order (all kept in LDS; ordering
+// through a workgroup-scope atomic, which costs no cache maintenance), and
+// writes the workgroup's triangle at
+// Y + blockIdx.x*ystride (leading dimension ldy).  With normalise (a single
+// workgroup, the final R), rows of a negative diagonal are negated.
 template <int NP, int RPL>
 __global__ void __launch_bounds__(64 * waves_per_block<NP>()) __attribute__((amdgpu_waves_per_eu(2)))
 tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
                  int64_t nwaves, double* __restrict__ Y, int64_t ldy, int64_t ystride, int normalise) {
     constexpr int WPB = waves_per_block<NP>();
-    __shared__ double Rsh[WPB][tri_size<NP>() + NP];
+    constexpr int STRIDE = tri_size<NP>() + NP;
+    constexpr int STAGE = staged_instance<NP, RPL>() ? kWave * RPL * NP : 2;
+    __shared__ double Rsh[WPB][STRIDE];
+    __shared__ __attribute__((aligned(16))) double stage[WPB][STAGE];
+    __shared__ int arrivals;
+    if (threadIdx.x == 0) arrivals = 0;
+    __syncthreads();
     const int lane = lane_id();
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
-    const int64_t w = (int64_t)blockIdx.x * WPB + wib;
+    const int64_t w0 = (int64_t)blockIdx.x * WPB;
+    const int64_t w = w0 + wib;
     if (w >= nwaves) return;
+    const int nvalid = (int)(nwaves - w0 < WPB ? nwaves - w0 : WPB);
     double* Rw = Rsh[wib];
     zero_r<NP>(Rw, lane);
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
-    fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
-    store_r<NP>(Rw, n, Y + w * ystride, ldy, normalise != 0, lane);
+    fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane, staged_instance<NP, RPL>() ? stage[wib] : nullptr);
+    if (nvalid > 1) {
+        int old = 0;
+        if (lane == 0) old = __hip_atomic_fetch_add(&arrivals, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+        old = __builtin_amdgcn_readfirstlane(old);
+        if (old != nvalid - 1) return;   // a sibling is still folding; it will combine
+        fold_block_triangles<NP, RPL>(&Rsh[0][0], STRIDE, nvalid, n, lane);
+        Rw = Rsh[0];
+    }
+    store_r<NP>(Rw, n, Y + (int64_t)blockIdx.x * ystride, ldy, normalise != 0, lane);
 }
 
 template <int NP, int RPL>
@@ -541,6 +687,45 @@ hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t r
     const int64_t blocks = ceil_div(nwaves, WPB);
     hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, X, m, n, ldx,
                        rows_per_wave, nwaves, Y, ldy, ystride, normalise);
+    return hipGetLastError();
+}
+
+// Last tree level of a TSQR for n <= 16 in one workgroup: wavefront w of
+// kTreeWaves folds a contiguous share of the k stacked triangles; the
+// wavefronts publish their triangles in `stage` (workgroup-scope ordering
+// through the barrier, all on one CU) and wavefront 0 folds those into R
+// with a non-negative diagonal.  Replaces the last two or three launches of
+// a fan-in tree.
+constexpr int kTreeWaves = 8;
+
+template <int NP, int RPL>
+__global__ void __launch_bounds__(64 * kTreeWaves) __attribute__((amdgpu_waves_per_eu(2)))
+tsqr_tree_block_kernel(const double* __restrict__ Y, int64_t k, int n, double* __restrict__ stage,
+                       double* __restrict__ R, int64_t ldr) {
+    __shared__ double Rsh[kTreeWaves][tri_size<NP>() + NP];
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double* Rw = Rsh[w];
+    const int64_t nn = (int64_t)n * n;
+    const int64_t per = ceil_div(k, kTreeWaves);
+    const int64_t t0 = (int64_t)w * per < k ? (int64_t)w * per : k;
+    const int64_t t1 = t0 + per < k ? t0 + per : k;
+    zero_r<NP>(Rw, lane);
+    fold_rows<NP, RPL>(Y, n, n, t0 * n, t1 * n, Rw, lane);
+    store_r<NP>(Rw, n, stage + w * nn, n, false, lane);
+    __syncthreads();
+    if (w == 0) {
+        zero_r<NP>(Rw, lane);
+        fold_rows<NP, RPL>(stage, n, n, 0, (int64_t)kTreeWaves * n, Rw, lane);
+        store_r<NP>(Rw, n, R, ldr, true, lane);
+    }
+}
+
+template <int NP, int RPL>
+hipError_t launch_tree_block(const double* Y, int64_t k, int n, double* stage, double* R, int64_t ldr,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL((tsqr_tree_block_kernel<NP, RPL>), dim3(1), dim3(64 * kTreeWaves), 0, stream, Y, k, n, stage,
+                       R, ldr);
     return hipGetLastError();
 }
 

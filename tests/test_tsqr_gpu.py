@@ -157,3 +157,27 @@ def test_config3_full_size_known_r(gpu, n):
     del X
     torch.cuda.empty_cache()
     assert oracle.rel_err_r(R, R0) <= E_R
+
+
+# Every compiled (n, rows_per_lane) instance, with one wavefront per CU so that
+# each wavefront folds at least four full panels plus part of a fifth: this
+# exercises the lane-private fold, the LDS-staged panel stream, register double
+# buffering, the workgroup combine and the tree, against the oracle.
+INSTANCES = [(1, 32), (1, 64), (2, 16), (2, 32), (3, 12), (3, 21), (4, 8), (4, 16), (5, 6), (5, 12), (6, 6),
+             (6, 10), (7, 4), (7, 9), (8, 4), (8, 8), (10, 6), (12, 5), (14, 4), (16, 4), (16, 2), (16, 3),
+             (24, 21), (32, 16), (32, 8), (40, 12), (48, 10), (56, 8), (64, 7), (64, 4)]
+
+
+@pytest.mark.parametrize("n,rpl", INSTANCES)
+def test_every_instance(gpu, n, rpl):
+    cus = torch.cuda.get_device_properties(gpu).multi_processor_count
+    panel = (64 if n <= 16 else 8) * rpl
+    m = cus * (4 * panel + panel // 2) + 333
+    print("case instance n=%d rpl=%d m=%d" % (n, rpl, m), flush=True)
+    X = wl.gaussian(m, n, seed=1000 + 10 * n + rpl)
+    q.qless_tune_set(n, 1, 0, rpl)
+    try:
+        R = run(X, gpu)
+    finally:
+        q.qless_tune_set(n, 0, 0, 0)
+    check(X, R)

@@ -15,8 +15,12 @@ def reset_tuning():
 
 
 def test_defaults_and_round_trip():
+    # default fan-in for n <= 16: one panel (64 lanes x rows_per_lane rows) of
+    # stacked n-row triangles per tree wavefront; 16 for wider n
     d = q.qless_tune_get(8)
-    assert d == {"waves_per_cu": 8, "fan_in": 16, "rows_per_lane": 8}
+    assert d == {"waves_per_cu": 8, "fan_in": 64 * 4 // 8, "rows_per_lane": 4}
+    assert q.qless_tune_get(16)["fan_in"] == 64 * 4 // 16
+    assert q.qless_tune_get(32)["fan_in"] == 16
     q.qless_tune_set(8, 12, 32, 4)
     assert q.qless_tune_get(8) == {"waves_per_cu": 12, "fan_in": 32, "rows_per_lane": 4}
 
@@ -40,7 +44,7 @@ def test_tuning_changes_the_plan():
 
 
 def test_variants_listed():
-    assert autotune.rows_per_lane_variants(8) == [8, 4]
+    assert autotune.rows_per_lane_variants(8) == [4, 8]
     assert autotune.rows_per_lane_variants(16)[0] == 4
 
 
