@@ -55,7 +55,8 @@ typedef enum {
 typedef enum {
     QLESS_METHOD_TSQR = 0,       /* qless_tsqr_r */
     QLESS_METHOD_CHOLQR2 = 1,    /* cholqr2_r */
-    QLESS_METHOD_SVQB = 2        /* svqb */
+    QLESS_METHOD_SVQB = 2,       /* svqb */
+    QLESS_METHOD_TSQR_UPDATE = 3 /* qless_tsqr_r_update */
 } qless_method;
 
 typedef enum {
@@ -90,6 +91,20 @@ size_t qless_workspace_bytes(int method, int64_t m, int64_t n);
 int qless_tsqr_r(const double *X, int64_t m, int64_t n, int64_t ldx,
                  double *R, int64_t ldr, void *work, size_t work_bytes,
                  hipStream_t stream);
+
+/*
+ * qless_tsqr_r_update -- running R over chunks of rows: R <- R([R; X]), the
+ * Q-less R of the previous rows stacked on the new ones (Alg. 2 applied to
+ * the stack, Sec. 1: the R of all rows seen so far).  R (n x n, ldr, upper
+ * triangular, any signs; entries below the diagonal are ignored) is read and
+ * overwritten with the new R, diagonal >= 0.  m may be 0 (then R only gets
+ * its row signs fixed).  Same launches as qless_tsqr_r plus one n x n copy;
+ * workspace from qless_workspace_bytes(QLESS_METHOD_TSQR_UPDATE, m, n).
+ * Arguments and errors as for qless_tsqr_r; X and R must not overlap.
+ */
+int qless_tsqr_r_update(const double *X, int64_t m, int64_t n, int64_t ldx,
+                        double *R, int64_t ldr, void *work, size_t work_bytes,
+                        hipStream_t stream);
 
 /*
  * cholqr2_r -- Q-less Cholesky-QR2 (Alg. 1): C = X^T X; R1 = chol(C);

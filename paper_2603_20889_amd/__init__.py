@@ -24,6 +24,7 @@ QLESS_ERR_WORKSPACE = -3
 QLESS_ERR_HIP = -4
 
 QLESS_METHOD_TSQR = 0
+QLESS_METHOD_TSQR_UPDATE = 3
 QLESS_METHOD_CHOLQR2 = 1
 QLESS_METHOD_SVQB = 2
 
@@ -33,7 +34,7 @@ QLESS_SVQB_QZ = 1
 QLESS_MAX_N = 64
 
 EXPORTED = (
-    "qless_status_string", "qless_version", "qless_workspace_bytes", "qless_tsqr_r",
+    "qless_status_string", "qless_version", "qless_workspace_bytes", "qless_tsqr_r", "qless_tsqr_r_update",
     "cholqr2_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
     "qless_timing_read", "qless_batch_plan_create", "qless_batch_plan_destroy",
     "qless_batch_plan_workspace_bytes", "qless_batch_plan_tiles", "qless_batch_plan_upload",
@@ -75,6 +76,8 @@ def load() -> ctypes.CDLL:
     lib.qless_workspace_bytes.restype = sz
     lib.qless_tsqr_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, sz, vp]
     lib.qless_tsqr_r.restype = ctypes.c_int
+    lib.qless_tsqr_r_update.argtypes = [vp, i64, i64, i64, vp, i64, vp, sz, vp]
+    lib.qless_tsqr_r_update.restype = ctypes.c_int
     lib.cholqr2_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
     lib.cholqr2_r.restype = ctypes.c_int
     lib.svqb.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, i64, vp, dbl, vp, vp, sz, vp]
@@ -175,6 +178,23 @@ def qless_tsqr_r(X, R=None, work=None):
                                  ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb,
                                  _stream(dev))
     _check(st, "qless_tsqr_r")
+    return R
+
+
+def qless_tsqr_r_update(X, R, work=None):
+    """Running R: R <- R([R; X]) in place (diag >= 0), for chunks of rows."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_TSQR_UPDATE, m, n, dev)
+        else:
+            wb = work.numel() * work.element_size()
+        st = load().qless_tsqr_r_update(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                                        ctypes.c_void_p(R.data_ptr()), R.stride(0),
+                                        ctypes.c_void_p(work.data_ptr()), wb, _stream(dev))
+    _check(st, "qless_tsqr_r_update")
     return R
 
 

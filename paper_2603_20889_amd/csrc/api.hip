@@ -152,6 +152,7 @@ size_t qless_workspace_bytes(int method, int64_t m, int64_t n) {
     const DeviceInfo& d = current_device_info();
     switch (method) {
         case QLESS_METHOD_TSQR: return make_tsqr_plan(m, n, d.num_cus).work_bytes;
+        case QLESS_METHOD_TSQR_UPDATE: return make_tsqr_update_plan(m, n, d.num_cus).work_bytes;
         case QLESS_METHOD_CHOLQR2:
         case QLESS_METHOD_SVQB: return gram_work_layout(make_gram_plan(m, n, d.num_cus), n, nullptr).bytes;
         default: return 0;
@@ -167,6 +168,17 @@ int qless_tsqr_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, 
     st = check_work(work, work_bytes, plan.work_bytes);
     if (st != QLESS_OK) return st;
     return launch_tsqr(X, m, n, ldx, R, ldr, work, plan, stream) == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int qless_tsqr_r_update(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr, void* work,
+                        size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, R, ldr);
+    if (st != QLESS_OK) return st;
+    const DeviceInfo& d = current_device_info();
+    TsqrPlan plan = make_tsqr_update_plan(m, n, d.num_cus);
+    st = check_work(work, work_bytes, plan.work_bytes);
+    if (st != QLESS_OK) return st;
+    return launch_tsqr_update(X, m, n, ldx, R, ldr, work, plan, stream) == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 
 int cholqr2_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr, int32_t* info,

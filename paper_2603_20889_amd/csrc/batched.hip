@@ -19,7 +19,7 @@
 #include <new>
 #include <vector>
 
-#include "tsqr_kernels.h"
+#include "batched_kernels.h"
 
 struct qless_batch_plan {
     std::vector<qless::BatchMat> mats;
@@ -27,6 +27,7 @@ struct qless_batch_plan {
     std::vector<qless::BatchGroup> groups;    // tree groups, level by level
     std::vector<int64_t> level_end;           // groups [level_end[l-1], level_end[l]) form level l
     int np_max = 1;
+    bool has_staged = false;                  // some matrix uses an LDS-staged instance (n <= 8)
     int64_t slot_doubles = 0;
     size_t off_tiles = 0, off_groups = 0, off_slots = 0, bytes = 0;
     int64_t nwaves = 0;
@@ -36,106 +37,40 @@ struct qless_batch_plan {
 namespace qless {
 namespace {
 
-constexpr int kFanIn = 16;
-constexpr int kBatchWpb = 2;  // wavefronts per workgroup of the batched kernels
+using batch_detail::kBatchWpb;
+using batch_detail::kFanIn;
 
-template <int NP, int RPL>
-__device__ __forceinline__ void batch_stage_tile(const BatchMat& M, int t, double* __restrict__ Rw,
-                                                 double* __restrict__ slots, int lane) {
-    using namespace tsqr_detail;
-    zero_r<NP>(Rw, lane);
-    const int64_t r0 = (int64_t)t * M.tile_rows;
-    const int64_t r1 = (r0 + M.tile_rows < M.m) ? r0 + M.tile_rows : M.m;
-    fold_rows<NP, RPL>(M.X, M.n, M.ldx, r0, r1, Rw, lane);
-    if (M.ntiles == 1) {
-        if (M.accumulate) fold_rows<NP, RPL>(M.R, M.n, M.ldr, 0, M.n, Rw, lane);
-        store_r<NP>(Rw, M.n, M.R, M.ldr, true, lane);
-    } else {
-        store_r<NP>(Rw, M.n, slots + M.slot_base + (int64_t)t * M.n * M.n, M.n, false, lane);
-    }
-}
-
-template <int NP, int RPL>
-__device__ __forceinline__ void batch_tree_group(const BatchMat& M, const BatchGroup& G, double* __restrict__ Rw,
-                                                 double* __restrict__ slots, int lane) {
-    using namespace tsqr_detail;
-    zero_r<NP>(Rw, lane);
-    fold_rows<NP, RPL>(slots + G.src, M.n, M.n, 0, (int64_t)G.gsize * M.n, Rw, lane);
-    if (G.dst < 0) {
-        if (M.accumulate) fold_rows<NP, RPL>(M.R, M.n, M.ldr, 0, M.n, Rw, lane);
-        store_r<NP>(Rw, M.n, M.R, M.ldr, true, lane);
-    } else {
-        store_r<NP>(Rw, M.n, slots + G.dst, M.n, false, lane);
-    }
-}
-
-// Instance per padded width: (NP, rows per lane) as in the single-matrix path.
-#define QLESS_BATCH_SWITCH(np, CALL)           \
-    switch (np) {                              \
-        case 1: CALL(1, 64); break;            \
-        case 2: CALL(2, 32); break;            \
-        case 4: CALL(4, 16); break;            \
-        case 8: CALL(8, 8); break;             \
-        case 16: CALL(16, 4); break;           \
-        case 32: CALL(32, 12); break;          \
-        default: CALL(64, 5); break;           \
-    }
-
-__global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
-batched_stage_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles, int64_t ntiles,
-                     int64_t nwaves, double* __restrict__ slots, int np_max) {
-    extern __shared__ double lds[];
-    const int lane = lane_id();
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
-    const int64_t w = (int64_t)blockIdx.x * kBatchWpb + wib;
-    if (w >= nwaves) return;
-    double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2 + np_max);
-    for (int64_t t = w; t < ntiles; t += nwaves) {
-        const int2 tl = tiles[t];
-        const BatchMat M = mats[tl.x];
-#define QLESS_STAGE_CALL(NP, RPL) batch_stage_tile<NP, RPL>(M, tl.y, Rw, slots, lane)
-        QLESS_BATCH_SWITCH(M.np, QLESS_STAGE_CALL)
-#undef QLESS_STAGE_CALL
-    }
-}
-
-__global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
-batched_tree_kernel(const BatchMat* __restrict__ mats, const BatchGroup* __restrict__ groups, int64_t ngroups,
-                    int64_t nwaves, double* __restrict__ slots, int np_max) {
-    extern __shared__ double lds[];
-    const int lane = lane_id();
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t w = (int64_t)blockIdx.x * kBatchWpb + wib;
-    if (w >= nwaves) return;
-    double* Rw = lds + (size_t)wib * (np_max * (np_max + 1) / 2 + np_max);
-    for (int64_t q = w; q < ngroups; q += nwaves) {
-        const BatchGroup G = groups[q];
-        const BatchMat M = mats[G.mat];
-#define QLESS_TREE_CALL(NP, RPL) batch_tree_group<NP, RPL>(M, G, Rw, slots, lane)
-        QLESS_BATCH_SWITCH(M.np, QLESS_TREE_CALL)
-#undef QLESS_TREE_CALL
-    }
-}
-
+// Padded width of the batched kernels for n (the widths of QLESS_BATCH_SWITCH).
 int batch_np(int64_t n) {
-    int np = 1;
-    while (np < n) np <<= 1;
-    return np;
+    static const int widths[] = {1, 2, 4, 8, 16, 24, 32, 40, 48, 56, 64};
+    for (int w : widths)
+        if (n <= w) return w;
+    return 64;
 }
 
+// Panel rows of the instance of a padded width (tiles are whole panels).
 int64_t batch_panel_rows(int np) {
     switch (np) {
-        case 1: return 64 * 64;
-        case 2: return 64 * 32;
-        case 4: return 64 * 16;
-        case 8: return 64 * 8;
+        case 1: return 64 * 32;
+        case 2: return 64 * 16;
+        case 4: return 64 * 8;
+        case 8: return 64 * 4;
         case 16: return 64 * 4;
-        case 32: return 8 * 12;
-        default: return 8 * 5;
+        case 24: return 8 * 21;
+        case 32: return 8 * 16;
+        case 40: return 8 * 12;
+        case 48: return 8 * 10;
+        case 56: return 8 * 8;
+        default: return 8 * 7;
     }
 }
 
 }  // namespace
+
+hipError_t launch_batched_stage(const BatchMat* mats, const int2* tiles, int64_t ntiles, int64_t nwaves,
+                                double* slots, int r_doubles, bool staged, hipStream_t s);
+hipError_t launch_batched_tree(const BatchMat* mats, const BatchGroup* groups, int64_t ngroups, int64_t nwaves,
+                               double* slots, int r_doubles, hipStream_t s);
 
 int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_bytes, int waves_per_cu,
                       qless_batch_plan** out) {
@@ -192,6 +127,7 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
             c = cn;
         }
         p->np_max = std::max(p->np_max, M.np);
+        if (M.np <= 8) p->has_staged = true;
         p->mats.push_back(M);
         for (int t = 0; t < M.ntiles; ++t) {
             const int64_t rows = std::min<int64_t>(tr, std::max<int64_t>(0, d[i].m - (int64_t)t * tr));
@@ -240,19 +176,16 @@ int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStrea
     char* b = static_cast<char*>(work);
     const BatchMat* mats = reinterpret_cast<const BatchMat*>(b);
     double* slots = reinterpret_cast<double*>(b + p->off_slots);
-    const size_t lds = (size_t)kBatchWpb * (p->np_max * (p->np_max + 1) / 2 + p->np_max) * sizeof(double);
-    hipLaunchKernelGGL(batched_stage_kernel, dim3((unsigned)ceil_div(p->nwaves, kBatchWpb)), dim3(64 * kBatchWpb),
-                       lds, s, mats, reinterpret_cast<const int2*>(b + p->off_tiles), (int64_t)p->tiles.size(),
-                       p->nwaves, slots, p->np_max);
-    if (hipGetLastError() != hipSuccess) return QLESS_ERR_HIP;
+    const int r_doubles = p->np_max * (p->np_max + 1) / 2 + p->np_max;
+    if (launch_batched_stage(mats, reinterpret_cast<const int2*>(b + p->off_tiles), (int64_t)p->tiles.size(),
+                             p->nwaves, slots, r_doubles, p->has_staged, s) != hipSuccess)
+        return QLESS_ERR_HIP;
     const BatchGroup* groups = reinterpret_cast<const BatchGroup*>(b + p->off_groups);
     int64_t lo = 0;
     for (int64_t hi : p->level_end) {
         const int64_t ng = hi - lo;
         const int64_t nw = std::min<int64_t>(ng, (int64_t)p->waves_cap);
-        hipLaunchKernelGGL(batched_tree_kernel, dim3((unsigned)ceil_div(nw, kBatchWpb)), dim3(64 * kBatchWpb), lds, s,
-                           mats, groups + lo, ng, nw, slots, p->np_max);
-        if (hipGetLastError() != hipSuccess) return QLESS_ERR_HIP;
+        if (launch_batched_tree(mats, groups + lo, ng, nw, slots, r_doubles, s) != hipSuccess) return QLESS_ERR_HIP;
         lo = hi;
     }
     return QLESS_OK;

@@ -1,0 +1,74 @@
+// Device side of the batched Q-less TSQR (paper Alg. 2 per matrix): the
+// per-tile and per-group folds and the instance switch shared by the stage-1
+// kernel (batched_stage.hip) and the tree kernel (batched_tree.hip).
+#pragma once
+
+#include "tsqr_kernels.h"
+
+namespace qless {
+namespace batch_detail {
+
+constexpr int kFanIn = 16;     // stacked triangles per tree group
+constexpr int kBatchWpb = 2;   // wavefronts per workgroup of the batched kernels
+// LDS staging buffer per wavefront for the staged instances (n <= 8): every
+// one of them streams panels of 2048 doubles (16 KB).  It shares the
+// wavefront's LDS region with the running triangle: a tile of width <= 8
+// needs at most 44 doubles of triangle, so the buffer starts at double 64,
+// and a wider tile (no staging) uses the whole region for its triangle.
+constexpr int kStageDoubles = 2048;
+constexpr int kStageOffset = 64;
+
+// Padded widths of the batched kernels and their rows per lane (the
+// single-matrix defaults of those widths).
+#define QLESS_BATCH_SWITCH(np, CALL)  \
+    switch (np) {                     \
+        case 1: CALL(1, 32); break;   \
+        case 2: CALL(2, 16); break;   \
+        case 4: CALL(4, 8); break;    \
+        case 8: CALL(8, 4); break;    \
+        case 16: CALL(16, 4); break;  \
+        case 24: CALL(24, 21); break; \
+        case 32: CALL(32, 16); break; \
+        case 40: CALL(40, 12); break; \
+        case 48: CALL(48, 10); break; \
+        case 56: CALL(56, 8); break;  \
+        default: CALL(64, 7); break;  \
+    }
+
+// Fold tile t of matrix M (rows [t*tile_rows, ...)) and write its triangle to
+// the matrix's level-0 slot, or, for a matrix of one tile, its final R
+// (stacking the previous R in with accumulate).
+template <int NP, int RPL>
+__device__ __forceinline__ void batch_stage_tile(const BatchMat& M, int t, double* __restrict__ Rw,
+                                                 double* __restrict__ slots, double* stage, int lane) {
+    using namespace tsqr_detail;
+    zero_r<NP>(Rw, lane);
+    const int64_t r0 = (int64_t)t * M.tile_rows;
+    const int64_t r1 = (r0 + M.tile_rows < M.m) ? r0 + M.tile_rows : M.m;
+    fold_rows<NP, RPL>(M.X, M.n, M.ldx, r0, r1, Rw, lane, staged_instance<NP, RPL>() ? stage : nullptr);
+    if (M.ntiles == 1) {
+        if (M.accumulate) fold_rows<NP, RPL>(M.R, M.n, M.ldr, 0, M.n, Rw, lane);
+        store_r<NP>(Rw, M.n, M.R, M.ldr, true, lane);
+    } else {
+        store_r<NP>(Rw, M.n, slots + M.slot_base + (int64_t)t * M.n * M.n, M.n, false, lane);
+    }
+}
+
+// Fold tree group G of matrix M: its gsize stacked triangles go to the next
+// level's slot, or, for the root, to the matrix's R.
+template <int NP, int RPL>
+__device__ __forceinline__ void batch_tree_group(const BatchMat& M, const BatchGroup& G, double* __restrict__ Rw,
+                                                 double* __restrict__ slots, int lane) {
+    using namespace tsqr_detail;
+    zero_r<NP>(Rw, lane);
+    fold_rows<NP, RPL>(slots + G.src, M.n, M.n, 0, (int64_t)G.gsize * M.n, Rw, lane);
+    if (G.dst < 0) {
+        if (M.accumulate) fold_rows<NP, RPL>(M.R, M.n, M.ldr, 0, M.n, Rw, lane);
+        store_r<NP>(Rw, M.n, M.R, M.ldr, true, lane);
+    } else {
+        store_r<NP>(Rw, M.n, slots + G.dst, M.n, false, lane);
+    }
+}
+
+}  // namespace batch_detail
+}  // namespace qless

@@ -218,6 +218,12 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus);
 int tsqr_tune_set(int64_t n, int waves_per_cu, int fan_in, int rows_per_lane);
 int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rows_per_lane);
 
+// Plan and launch of R <- R([R; X]) (qless_tsqr_r_update): the previous R
+// joins the stacked triangles of X as one more.
+TsqrPlan make_tsqr_update_plan(int64_t m, int64_t n, int num_cus);
+hipError_t launch_tsqr_update(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
+                              void* work, const TsqrPlan& plan, hipStream_t stream);
+
 // Enqueue a full TSQR (stage 1 + tree + sign normalisation) into `work`.
 // Arguments have been validated by the caller.
 hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R,

@@ -168,35 +168,22 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     return p;
 }
 
-hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
-                       void* work, const TsqrPlan& plan, hipStream_t stream) {
-    if (plan.levels > 0 && work == nullptr) return hipErrorInvalidValue;  // the tree needs its buffers
-    const Instance* in = find_instance(plan.npad, plan.rows_per_lane);
-    if (!in) return hipErrorInvalidValue;
+namespace {
+
+// Tree of Alg. 2 over the k >= 2 stacked triangles in src (the other buffer,
+// dst, takes intermediate levels): wavefront g of a level folds the fan_in
+// triangles g*fan_in .. of the previous level, read as one tall
+// (fan_in*n) x n matrix, and each workgroup leaves one triangle; the last
+// level writes R with a non-negative diagonal.
+hipError_t launch_tree(const Instance* in, const TsqrPlan& plan, double* src, double* dst, int64_t k, int64_t n,
+                       double* R, int64_t ldr, hipStream_t stream) {
     const int ni = (int)n;
     const int64_t nn = n * n;
-    hipError_t e;
-    timing_begin(kTimeTsqrStage1, stream);
-    if (plan.k1 == 1) {
-        e = in->fn(X, m, ni, ldx, plan.rows_per_wave, plan.k0, R, ldr, 0, 1, stream);
-        timing_end(kTimeTsqrStage1, stream);
-        return e;
-    }
-    double* src = static_cast<double*>(work);
-    double* dst = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
-    e = in->fn(X, m, ni, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, stream);
-    timing_end(kTimeTsqrStage1, stream);
-    // tree (Alg. 2, second call, repeated): wavefront g of a level folds the
-    // fan_in triangles g*fan_in .. of the previous level, read as one tall
-    // (fan_in*n) x n matrix, and each workgroup leaves one triangle.
     const int64_t rpw = (int64_t)plan.fan_in * n;
     TreeFn tree = plan.block_tree ? find_tree(plan.npad, plan.rows_per_lane) : nullptr;
-    int64_t k = plan.k1;
+    hipError_t e = hipSuccess;
     while (e == hipSuccess && k > 1) {
-        if (tree && k * n <= (int64_t)tsqr_detail::kTreeWaves * plan.tree_rows) {
-            e = tree(src, k, ni, dst, R, ldr, stream);
-            break;
-        }
+        if (tree && k * n <= (int64_t)tsqr_detail::kTreeWaves * plan.tree_rows) return tree(src, k, ni, dst, R, ldr, stream);
         const int64_t nw = ceil_div(k, plan.fan_in);
         const int64_t kn = ceil_div(nw, plan.wpb);
         if (kn == 1) {
@@ -210,6 +197,77 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
         k = kn;
     }
     return e;
+}
+
+// Upper triangle of R (ld ldr) into an n x n slot (ld n), zeros below.
+__global__ void copy_upper_kernel(const double* __restrict__ R, int64_t ldr, int n, double* __restrict__ out) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, c = e - i * n;
+        out[e] = c >= i ? R[(int64_t)i * ldr + c] : 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
+                       void* work, const TsqrPlan& plan, hipStream_t stream) {
+    if (plan.levels > 0 && work == nullptr) return hipErrorInvalidValue;  // the tree needs its buffers
+    const Instance* in = find_instance(plan.npad, plan.rows_per_lane);
+    if (!in) return hipErrorInvalidValue;
+    const int64_t nn = n * n;
+    hipError_t e;
+    timing_begin(kTimeTsqrStage1, stream);
+    if (plan.k1 == 1) {
+        e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, R, ldr, 0, 1, stream);
+        timing_end(kTimeTsqrStage1, stream);
+        return e;
+    }
+    double* src = static_cast<double*>(work);
+    double* dst = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
+    e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, stream);
+    timing_end(kTimeTsqrStage1, stream);
+    if (e != hipSuccess) return e;
+    return launch_tree(in, plan, src, dst, plan.k1, n, R, ldr, stream);
+}
+
+TsqrPlan make_tsqr_update_plan(int64_t m, int64_t n, int num_cus) {
+    TsqrPlan p = make_tsqr_plan(m, n, num_cus);
+    // the previous R joins the stage-1 triangles as one more, so there is
+    // always a tree and both stacked buffers hold k1 + 1 triangles
+    const size_t blk = (size_t)n * (size_t)n * sizeof(double);
+    const size_t ybytes = align_up((size_t)std::max<int64_t>(p.k1 + 1, tsqr_detail::kTreeWaves) * blk, 256);
+    p.ybytes_a = ybytes;
+    p.ybytes_b = ybytes;
+    p.work_bytes = 2 * ybytes;
+    if (p.levels == 0) p.levels = 1;
+    return p;
+}
+
+hipError_t launch_tsqr_update(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
+                              void* work, const TsqrPlan& plan, hipStream_t stream) {
+    if (work == nullptr) return hipErrorInvalidValue;
+    const Instance* in = find_instance(plan.npad, plan.rows_per_lane);
+    if (!in) return hipErrorInvalidValue;
+    const int64_t nn = n * n;
+    double* src = static_cast<double*>(work);
+    double* dst = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
+    int64_t k = 0;
+    hipError_t e = hipSuccess;
+    if (m > 0) {
+        timing_begin(kTimeTsqrStage1, stream);
+        e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, stream);
+        timing_end(kTimeTsqrStage1, stream);
+        k = plan.k1;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(copy_upper_kernel, dim3(1), dim3(256), 0, stream, R, ldr, (int)n, src + k * nn);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ++k;
+    if (k == 1) {   // no new rows: R([R]) is R with its diagonal made non-negative
+        return in->fn(src, n, (int)n, n, n, 1, R, ldr, 0, 1, stream);
+    }
+    return launch_tree(in, plan, src, dst, k, n, R, ldr, stream);
 }
 
 }  // namespace qless

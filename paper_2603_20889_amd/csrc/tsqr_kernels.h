@@ -247,6 +247,28 @@ __device__ __forceinline__ void load_panel_1d_tail(double (&x)[RPL][NP], const d
     }
 }
 
+// Interior panel of a padded width (n < NP): one 8-byte buffer load per
+// column, the offset of a column c >= n clamped to column 0 (in bounds) and
+// its value replaced by 0.
+template <int NP, int RPL>
+__device__ __forceinline__ void load_panel_1d_padded(double (&x)[RPL][NP], const double* __restrict__ X, int n,
+                                                     int64_t ldx, int64_t base, int lane) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+    const int vo = lane * (int)(ldx * 8);
+    const int so = (int)(ldx * 8 * kWave);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            const bool ok = c < n;
+            const double v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo + (ok ? c : 0) * 8,
+                                                                                             so * i, 0));
+            x[i][c] = ok ? v : 0.0;
+        }
+    }
+}
+
 // Double buffering pays when two panels fit the registers next to the fold's
 // temporaries: the next panel is then in flight while the current one is
 // folded.
@@ -395,6 +417,13 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
     double* Cw = Rw + tri_size<NP>();   // per-wavefront coefficient exchange
     double xa[RPL][NP];
     int64_t base = r_begin;
+    if (n < NP && PANEL * ldx * 8 < 0x7FFFFFFF) {
+        // padded width: interior panels one at a time, cross-lane fold
+        for (; base + PANEL <= r_end; base += PANEL) {
+            load_panel_1d_padded<NP, RPL>(xa, X, n, ldx, base, lane);
+            FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
+        }
+    }
     if constexpr (lane_private<NP>()) {
         if (nfull >= kLanePrivateMin) {
             if constexpr (staged_instance<NP, RPL>()) {
@@ -522,13 +551,29 @@ __device__ __forceinline__ void load_panel_2d(double (&x)[RPL][NP / kG2], const 
     if (fast && base + PANEL <= r_end) {
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
-        const int vo = (int)((rg * ldx + cg) * 8);
+        if (n == NP) {
+            const int vo = (int)((rg * ldx + cg) * 8);
 #pragma unroll
-        for (int i = 0; i < RPL; ++i)
+            for (int i = 0; i < RPL; ++i)
 #pragma unroll
-            for (int u = 0; u < NC; ++u)
-                x[i][u] = __builtin_bit_cast(
-                    double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, (int)((kRG2 * i * ldx + kG2 * u) * 8), 0));
+                for (int u = 0; u < NC; ++u)
+                    x[i][u] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, (int)((kRG2 * i * ldx + kG2 * u) * 8), 0));
+        } else {
+            // padded width: a column c >= n reads column 0 (in bounds) and is zeroed
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int c = cg + kG2 * u;
+                const bool ok = c < n;
+                const int vo = (int)((rg * ldx + (ok ? c : 0)) * 8);
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const double v = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, (int)(kRG2 * i * ldx * 8), 0));
+                    x[i][u] = ok ? v : 0.0;
+                }
+            }
+        }
     } else {
         const int64_t left = r_end - base - rg;
         const double* x0 = X + (left > 0 ? base + rg : 0) * ldx;
@@ -551,7 +596,7 @@ __device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n
     constexpr int NC = NP / kG2;
     constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
     if (r_begin >= r_end) return;
-    const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
+    const bool fast = PANEL * ldx * 8 < 0x7FFFFFFF;   // interior panels: buffer loads (any n <= NP)
     for (int64_t base = r_begin; base < r_end; base += PANEL) {
         double x[RPL][NC];
         load_panel_2d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);

@@ -12,6 +12,9 @@ Serving loop (continuous batching, not a queue alone):
   * every step folds the next chunk of rows of EVERY active request into its
     running R, all in one batched launch (``BatchPlan`` with accumulate), so
     work of requests that arrived at different times overlaps on the device;
+    requests with little work left get all of it and the rest of the step's
+    byte budget goes to the others oldest first, so short requests do not wait
+    behind long ones and long ones keep their arrival order;
     R([R_old; chunk]) = R([rows so far; chunk]) makes the n x n R the whole
     per-request state, and it stays on the device;
   * a request whose rows are exhausted gets its back substitution on the
@@ -57,21 +60,37 @@ class Request:
 
 
 class GpuExecutor:
-    """Device executor: request data and running R live in HBM; each step is
-    one persistent batched launch over all active requests' chunks."""
+    """Device executor: request data and running R live in HBM.
 
-    def __init__(self, device, tile_bytes: int = 1 << 20, data_fn: Optional[Callable] = None):
+    mode "batched": each step is one persistent batched launch (plus tree
+    levels) over all active requests' chunks (``BatchPlan`` with accumulate).
+    mode "update": each step enqueues, per active request, the single-matrix
+    kernels on its chunk with the previous R stacked in
+    (``qless_tsqr_r_update``); the chunks of a step run back to back on one
+    stream, and the device is waited for when a result is read."""
+
+    def __init__(self, device, tile_bytes: int = 1 << 20, data_fn: Optional[Callable] = None,
+                 mode: str = "batched"):
         import torch
 
         import paper_2603_20889_amd as q
         import workloads
+        if mode not in ("batched", "update"):
+            raise ValueError("mode must be 'batched' or 'update'")
         self.q = q
         self.torch = torch
         self.device = device
         self.tile_bytes = tile_bytes
+        self.mode = mode
         self._data = data_fn or (lambda r: workloads.ls_request_data(r.m, r.n, r.seed, device=device)[0])
         self.stream = torch.cuda.current_stream(device)
         self.steps = 0
+        self._work = None
+
+    def _workspace(self, nbytes: int):
+        if self._work is None or self._work.numel() < nbytes:
+            self._work = self.torch.empty(max(nbytes, 1 << 20), dtype=self.torch.uint8, device=self.device)
+        return self._work
 
     def admit(self, r: Request):
         torch = self.torch
@@ -80,13 +99,27 @@ class GpuExecutor:
         r.state = {"Ab": Ab, "R": R}
 
     def step(self, chunks):
-        Xs = [r.state["Ab"][lo:hi] for r, lo, hi in chunks]
-        Rs = [r.state["R"] for r, _, _ in chunks]
-        plan = self.q.BatchPlan(Xs, Rs=Rs, accumulate=[True] * len(chunks), tile_bytes=self.tile_bytes)
-        plan.run()
-        self.torch.cuda.current_stream(self.device).synchronize()
-        plan.close()
+        if self.mode == "update":
+            for r, lo, hi in chunks:
+                need = self.q.qless_workspace_bytes(self.q.QLESS_METHOD_TSQR_UPDATE, hi - lo, r.n + 1)
+                self.q.qless_tsqr_r_update(r.state["Ab"][lo:hi], r.state["R"], work=self._workspace(need))
+        else:
+            Xs = [r.state["Ab"][lo:hi] for r, lo, hi in chunks]
+            Rs = [r.state["R"] for r, _, _ in chunks]
+            plan = self.q.BatchPlan(Xs, Rs=Rs, accumulate=[True] * len(chunks), tile_bytes=self.tile_bytes)
+            plan.run()
+            self.torch.cuda.current_stream(self.device).synchronize()
+            plan.close()
         self.steps += 1
+
+    def solve(self, r: Request):
+        """One request alone with the plain single-matrix call (the baseline):
+        R([A b]) by qless_tsqr_r in one call, then the back substitution."""
+        Ab = self._data(r)
+        R = self.q.qless_tsqr_r(Ab)
+        r.state = {"Ab": Ab, "R": R}
+        self.steps += 1
+        self.finish(r)
 
     def finish(self, r: Request):
         x, res, info = self.q.qless_lstsq_finish(r.state["R"])
@@ -101,10 +134,11 @@ class LstsqServer:
     """Admission by HBM footprint, continuous batching of row chunks."""
 
     def __init__(self, executor, hbm_budget_bytes: int, step_bytes: int = 1 << 30, max_active: int = 256,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, short_bytes: Optional[int] = None):
         self.ex = executor
         self.budget = int(hbm_budget_bytes)
         self.step_bytes = int(step_bytes)
+        self.short_bytes = int(short_bytes if short_bytes is not None else step_bytes // 2)
         self.max_active = int(max_active)
         self.clock = clock
         self.queue: collections.deque[Request] = collections.deque()
@@ -136,18 +170,33 @@ class LstsqServer:
         self.max_active_seen = max(self.max_active_seen, len(self.active))
 
     def _chunks(self):
-        """Next row range of every active request.  The step's byte budget is
-        shared evenly, with at least one 4096-row chunk per request."""
+        """Next row ranges, within the step's byte budget: (1) requests whose
+        remaining work is at most short_bytes get all of it (smallest first),
+        so short requests finish at once instead of queueing behind long
+        ones; (2) what is left goes to the other requests oldest first, so
+        long requests keep their arrival order.  A request may get no rows in
+        a step; each step is one batch over the requests that got some."""
         if not self.active:
             return []
-        share = max(self.step_bytes // len(self.active), 1)
-        out = []
-        for r in self.active:
-            rows = max(4096, share // (8 * (r.n + 1)))
-            lo = r.rows_done
-            hi = min(r.m, lo + rows)
-            out.append((r, lo, hi))
-        return out
+        rows = {r.id: 0 for r in self.active}
+        left = lambda r: (r.m - r.rows_done - rows[r.id]) * 8 * (r.n + 1)
+        budget = self.step_bytes
+        for r in sorted(self.active, key=left):
+            if budget <= 0 or left(r) > self.short_bytes:
+                break
+            take = min(left(r), budget) // (8 * (r.n + 1))
+            rows[r.id] += take
+            budget -= take * 8 * (r.n + 1)
+        for r in sorted(self.active, key=lambda r: (r.arrival_s, r.id)):
+            if budget <= 0:
+                break
+            take = min(left(r), budget) // (8 * (r.n + 1))
+            rows[r.id] += take
+            budget -= take * 8 * (r.n + 1)
+        if all(v == 0 for v in rows.values()):           # budget below one row: still progress
+            r = min(self.active, key=lambda r: (r.arrival_s, r.id))
+            rows[r.id] = 1
+        return [(r, r.rows_done, r.rows_done + rows[r.id]) for r in self.active if rows[r.id] > 0]
 
     def step(self):
         self._admit()
@@ -155,10 +204,11 @@ class LstsqServer:
         if not chunks:
             return False
         self.ex.step(chunks)
-        still = []
         for r, lo, hi in chunks:
             r.rows_done = hi
-            if hi >= r.m:
+        still = []
+        for r in self.active:                   # requests without rows this step stay active
+            if r.rows_done >= r.m:
                 self.ex.finish(r)
                 r.done_s = self.now()
                 self.in_use -= r.footprint
@@ -181,7 +231,7 @@ class LstsqServer:
                 if pending:
                     wait = pending[0].arrival_s - self.now()
                     if wait > 0:
-                        time.sleep(min(wait, 0.01))
+                        time.sleep(min(wait, 0.001))
                 elif self.queue and not self.active:
                     raise RuntimeError("request does not fit the HBM budget")
         return self.stats()
@@ -203,7 +253,8 @@ class LstsqServer:
 
 
 class FifoServer:
-    """Baseline: one request per launch, in arrival order (no batching)."""
+    """Baseline: one request at a time in arrival order, each solved by the
+    plain single-matrix call (no batching)."""
 
     def __init__(self, executor, clock: Callable[[], float] = time.perf_counter):
         self.ex = executor
@@ -219,10 +270,13 @@ class FifoServer:
             now = self.clock() - self.t0
             if realtime and r.arrival_s > now:
                 time.sleep(r.arrival_s - now)
-            self.ex.admit(r)
             r.admit_s = self.clock() - self.t0
-            self.ex.step([(r, 0, r.m)])
-            self.ex.finish(r)
+            if hasattr(self.ex, "solve"):
+                self.ex.solve(r)
+            else:
+                self.ex.admit(r)
+                self.ex.step([(r, 0, r.m)])
+                self.ex.finish(r)
             r.done_s = self.clock() - self.t0
             self.done.append(r)
         lat = sorted(r.latency_s for r in self.done)

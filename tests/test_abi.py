@@ -99,3 +99,14 @@ def test_small_problems_plan_one_wavefront():
         assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, n, n) == 256
     assert (q.qless_workspace_bytes(q.QLESS_METHOD_SVQB, 10_000, 64)
             >= q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2, 10_000, 64))
+
+
+def test_update_argument_and_workspace_errors():
+    lib = q.load()
+    # R is read and written, so it is always required; the update always needs a workspace
+    assert lib.qless_tsqr_r_update(FAKE, 100, 4, 4, NULL, 4, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_tsqr_r_update(FAKE, 100, 65, 65, FAKE, 65, FAKE, 1 << 20, NULL) == q.QLESS_ERR_UNSUPPORTED
+    need = q.qless_workspace_bytes(q.QLESS_METHOD_TSQR_UPDATE, 0, 8)
+    assert need >= 2 * 8 * 8 * 8 * 8 > q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 0, 8)
+    assert lib.qless_tsqr_r_update(NULL, 0, 8, 8, FAKE, 8, NULL, need, NULL) == q.QLESS_ERR_WORKSPACE
+    assert lib.qless_tsqr_r_update(FAKE, 10_000, 8, 8, FAKE, 8, FAKE, need - 1, NULL) == q.QLESS_ERR_WORKSPACE

@@ -92,3 +92,20 @@ def test_fifo_baseline_runs():
     reqs = small_requests(5, seed=4)
     st = FifoServer(OracleExecutor()).run(reqs, realtime=False)
     assert st["completed"] == 5
+
+
+def test_short_requests_bypass_and_long_ones_keep_order():
+    """Step budget policy: a short request finishes in the first step even
+    behind long ones, alongside the oldest long one; the long ones complete
+    in arrival order."""
+    a = Request(id=0, arrival_s=0.0, m=120_000, n=4, seed=21)
+    b = Request(id=1, arrival_s=0.001, m=120_000, n=4, seed=22)
+    c = Request(id=2, arrival_s=0.002, m=6_000, n=4, seed=23)
+    ex = OracleExecutor()
+    srv = LstsqServer(ex, hbm_budget_bytes=1 << 30, step_bytes=1_000_000)
+    srv.run([a, b, c], realtime=False)
+    first = {ch[0]: ch[2] - ch[1] for ch in ex.chunks_per_step[0]}
+    assert first[2] == c.m                     # the short one, whole
+    assert first[0] > 0 and 1 not in first     # the oldest long one takes the rest
+    assert a.done_s <= b.done_s
+    assert all(c.done_s <= r.done_s for r in (a, b))

@@ -12,11 +12,12 @@ from paper_2603_20889_amd.server import FifoServer, GpuExecutor, LstsqServer, ma
 pytestmark = pytest.mark.gpu
 
 
-def test_served_equals_alone(gpu):
+@pytest.mark.parametrize("mode", ["batched", "update"])
+def test_served_equals_alone(gpu, mode):
     reqs = make_requests(24, rate_per_s=1e6, seed=17, mlo=1e4, mhi=4e5, nlo=3, nhi=20)
-    srv = LstsqServer(GpuExecutor(gpu), hbm_budget_bytes=200 << 20, step_bytes=64 << 20, max_active=8)
+    srv = LstsqServer(GpuExecutor(gpu, mode=mode), hbm_budget_bytes=200 << 20, step_bytes=64 << 20, max_active=8)
     st = srv.run(reqs, realtime=False)
-    print("case served: %s" % st, flush=True)
+    print("case served %s: %s" % (mode, st), flush=True)
     assert st["completed"] == len(reqs)
     assert srv.ex.steps > 1
     for r in reqs:

@@ -181,3 +181,21 @@ def test_every_instance(gpu, n, rpl):
     finally:
         q.qless_tune_set(n, 0, 0, 0)
     check(X, R)
+
+
+@pytest.mark.parametrize("n,chunks", [(4, [0, 50_000, 1, 300_000]), (8, [70_000, 0, 2_000_000]),
+                                      (13, [5_000, 400_000]), (16, [1_000_000, 3]), (33, [20_000, 150_000])])
+def test_running_update(gpu, n, chunks):
+    """qless_tsqr_r_update over successive row chunks (empty ones included)
+    equals the R of all rows at once (Alg. 2 on the stack [R_old; X])."""
+    m = sum(chunks)
+    X = wl.gaussian(m, n, seed=77 + n)
+    print("case update n=%d chunks=%s" % (n, chunks), flush=True)
+    Xd = torch.from_numpy(X).to(gpu)
+    R = torch.zeros((n, n), dtype=torch.float64, device=gpu)
+    lo = 0
+    for c in chunks:
+        q.qless_tsqr_r_update(Xd[lo:lo + c], R)
+        lo += c
+    torch.cuda.synchronize(gpu)
+    check(X, R.cpu().numpy())
