@@ -289,8 +289,15 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25):
                             "tsqr_frac_fp64": round(tsqr_flops(m, ns) / (k_avg * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)})
                 if flush is None:
                     rec["tsqr_step_ms"] = round(t_ms, 5)
-                c_ms, _ = time_calls(lambda: q.cholqr2_r(Xs, work=None), max(3, steps // 4), 1)
+                cw, _ = q._workspace(q.QLESS_METHOD_CHOLQR2, m, ns, dev)
+                q.timing_reset()
+                q.timing_enable(True)
+                c_ms, _ = time_calls(lambda: q.cholqr2_r(Xs, work=cw), max(3, steps // 4), 1)
+                q.timing_enable(False)
+                g_ms, g_cnt = q.timing_read("gram")
+                q.timing_reset()
                 rec.update({"cholqr2_ms": round(c_ms, 5),
+                            "cholqr2_gram_ms_per_pass": round(g_ms / max(g_cnt, 1), 5),
                             "cholqr2_GBps": round(gram2_bytes(m, ns) / (c_ms * 1e-3) / 1e9, 1),
                             "cholqr2_TFps": round(5.0 * m * ns * ns / (c_ms * 1e-3) / 1e12, 2)})
                 del flush

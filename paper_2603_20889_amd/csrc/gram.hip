@@ -5,104 +5,225 @@
 //                                    (CholQR2) or M = U1 L1^{-1/2} (SVQB2),
 //                                    never storing X M.
 //
-// Layout: a wavefront splits its 64 lanes into G = 64/NP row groups of NP
-// lanes; lane (g, i) owns column i of the rows of group g.  X is staged
-// through a wavefront-private LDS slab loaded with coalesced row-major reads
-// (lane (g, i) loads exactly its own entries), so every lane can read a
-// whole row as a broadcast.  Lane (g, i) then forms y_i = sum_k x_k M_ki
-// (M column i in registers), writes it back to LDS, and accumulates
-// acc_c += y_i y_c for every c: row i of the wavefront's partial Gram
-// matrix.  At the end the G groups are summed and each wavefront writes its
-// n x n partial to the workspace; gram_sum adds the partials in a fixed order
-// (no atomics, so results are reproducible bit for bit).
+// n <= 8 (gram_rows_kernel): each lane holds full rows (the TSQR panel
+// loads), forms y = x M on the VALU and accumulates the n(n+1)/2 products of
+// the upper triangle; one transposed butterfly sums them at the end.
+//
+// n > 8 (gram_mfma_kernel): FP64 matrix cores, v_mfma_f64_16x16x4f64
+// (D[16x16] += A[16x4] B[4x16]; lane l holds A[l%16][l/16] and B[l/16][l%16],
+// and D[4v + l/16][l%16] in its v-th accumulator, as measured on gfx950).
+// Columns are cut into NB = ceil(n/16) blocks of 16.  For a block of 16 rows
+// the Gram operand of column block J and row quartet v is
+//   y_J[v] = Y[r0 + 4v + l/16][16J + l%16],
+// so tile (I, J) of C accumulates mfma(y_I[v], y_J[v]) over v and over the
+// row blocks (upper tiles only; C is symmetric).  In pass 2, Y = X M is itself
+// a product on the matrix cores: with A = X[r0 + l%16][4k + l/16] and
+// B = M[4k + l/16][16J + l%16], the accumulator of column block J after the
+// n/4 steps k holds exactly y_J[v] in its v-th register -- no transpose.
+//
+// Every wavefront writes its n x n partial to the workspace and gram_sum adds
+// the partials in a fixed order (no atomics: results are reproducible bit for
+// bit).
 #include "tsqr_kernels.h"
 
 namespace qless {
 namespace {
 
-template <int NP>
-struct GramShape {
-    static constexpr int G = kWave / NP;            // row groups per wavefront
-    static constexpr int SR = 512 / NP;             // rows per LDS slab (512 elements)
-    static constexpr int LD = NP >= 8 ? NP + 2 : NP; // padded row stride in LDS
-    static constexpr int PER_LANE = SR / G;         // rows per lane per slab (= 8)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Operands of U consecutive 16-row blocks [r0, r0 + 16U) for
+// gram_mfma_kernel, from a buffer resource based at row r0 (lane offset in a
+// VGPR, row stride and column in SGPR / immediate offsets).  For sub-block u
+// (rows r0 + 16u ..):
+//   pass 1: v[u][4J + q] = X[16u + 4q + hi][16J + lo]  (full 128-byte rows per load)
+//   pass 2: v[u][k]      = X[16u + lo][4k + hi]         (A operand of Y = X M)
+// Without GUARD (all 16U rows present and n a multiple of 16) the loads are
+// unguarded.  With GUARD, the row and the column of each lane are clamped in
+// bounds and what a clamped lane read is replaced by 0.  U is chosen so that a stage holds 16 to 32 doubles per lane;
+// with two stages in registers, 8 KB or more per wavefront are in flight.
+template <int NB>
+constexpr int gram_sub_blocks() {
+    return NB == 1 ? 8 : NB == 2 ? 4 : NB == 3 ? 2 : 1;
+}
+
+template <int NB>
+struct GramStage {
+    double v[gram_sub_blocks<NB>()][4 * NB];
 };
 
-template <int NP, bool HAS_M>
-__global__ void __launch_bounds__(256)
-gram_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-            int64_t nwaves, const double* __restrict__ M, double* __restrict__ Cpart) {
-    using S = GramShape<NP>;
-    __shared__ double slab[4][2][S::SR * S::LD];
-    const int lane = lane_id();
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (SGPR)
-    const int64_t w = (int64_t)blockIdx.x * 4 + wib;
-    if (w >= nwaves) return;
-    const int g = lane / NP;
-    const int i = lane % NP;
-    double* xs = slab[wib][0];
-    double* ys = slab[wib][1];
-
-    double mcol[NP];
-    if (HAS_M) {
+template <int NB, bool HAS_M, bool GUARD>
+__device__ __forceinline__ void gram_load_stage(GramStage<NB>& b, const double* __restrict__ X, int n, int64_t ldx,
+                                                int64_t r0, int64_t r_end, int lo, int hi) {
+    constexpr int U = gram_sub_blocks<NB>();
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + r0 * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+    const int row_bytes = (int)(ldx * 8);
+    const int64_t rows_left = r_end - r0;
+    if constexpr (HAS_M) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) mcol[k] = (k < n && i < n) ? M[(int64_t)k * n + i] : 0.0;
-    }
-    double acc[NP];
+        for (int u = 0; u < U; ++u) {
+            const int r = 16 * u + lo;
+            const bool rok = !GUARD || r < rows_left;
 #pragma unroll
-    for (int c = 0; c < NP; ++c) acc[c] = 0.0;
-
-    const int64_t r_begin = w * rows_per_wave;
-    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
-    for (int64_t base = r_begin; base < r_end; base += S::SR) {
-        // coalesced load: lane (g, i) fetches rows g + G*t, column i
-#pragma unroll
-        for (int t = 0; t < S::PER_LANE; ++t) {
-            const int r = g + S::G * t;
-            const int64_t row = base + r;
-            double v = 0.0;
-            if (row < r_end && i < n) v = X[row * ldx + i];
-            xs[r * S::LD + i] = v;
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int t = 0; t < S::PER_LANE; ++t) {
-            const int r = g + S::G * t;
-            const double* xr = xs + r * S::LD;
-            if (HAS_M) {
-                double y = 0.0;
-#pragma unroll
-                for (int k = 0; k < NP; ++k) y = fma(xr[k], mcol[k], y);
-                ys[r * S::LD + i] = y;
+            for (int k = 0; k < 4 * NB; ++k) {
+                const int c = 4 * k + hi;
+                const bool ok = !GUARD || (rok && c < n);
+                const int off =
+                    GUARD ? (rok ? r : 0) * row_bytes + (c < n ? c : 0) * 8 : lo * row_bytes + hi * 8 + 32 * k;
+                const double x = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, GUARD ? 0 : 16 * u * row_bytes, 0));
+                b.v[u][k] = ok ? x : 0.0;
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        const double* src = HAS_M ? ys : xs;
+    } else {
 #pragma unroll
-        for (int t = 0; t < S::PER_LANE; ++t) {
-            const int r = g + S::G * t;
-            const double* yr = src + r * S::LD;
-            const double yi = yr[i];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int c = 0; c < NP; ++c) acc[c] = fma(yi, yr[c], acc[c]);
-        }
-        __builtin_amdgcn_wave_barrier();
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * u + 4 * q + hi;
+                const bool rok = !GUARD || r < rows_left;
+#pragma unroll
+                for (int J = 0; J < NB; ++J) {
+                    const int c = 16 * J + lo;
+                    const bool ok = !GUARD || (rok && c < n);
+                    const int off =
+                        GUARD ? (rok ? r : 0) * row_bytes + (c < n ? c : 0) * 8 : hi * row_bytes + lo * 8 + 128 * J;
+                    const double x = __builtin_bit_cast(
+                        double,
+                        __builtin_amdgcn_raw_buffer_load_b64(rs, off, GUARD ? 0 : (16 * u + 4 * q) * row_bytes, 0));
+                    b.v[u][4 * J + q] = ok ? x : 0.0;
+                }
+            }
     }
+}
 
-    // sum the G row groups: lanes i, i + NP, i + 2NP, ...
+// Number of accumulators: one per upper tile, and four partial sums of the
+// single tile when NB == 1 so that consecutive products never wait for each
+// other's result.
+template <int NB>
+constexpr int gram_accs() {
+    return NB == 1 ? 4 : NB * (NB + 1) / 2;
+}
+
+template <int NB, bool HAS_M>
+__device__ __forceinline__ void gram_stage(const GramStage<NB>& b, const double* __restrict__ Ms,
+                                           f64x4 (&acc)[gram_accs<NB>()], int lo, int hi) {
+    constexpr int NPAD = 16 * NB;
+    constexpr int U = gram_sub_blocks<NB>();
 #pragma unroll
-    for (int c = 0; c < NP; ++c) {
-        double v = acc[c];
+    for (int u = 0; u < U; ++u) {
+        f64x4 y[NB];
+        if constexpr (HAS_M) {
+            // M stays in LDS: its operands are re-read for every block rather
+            // than held in NB * 4NB registers
+            asm volatile("" ::: "memory");
 #pragma unroll
-        for (int d = NP; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
-        acc[c] = v;
+            for (int J = 0; J < NB; ++J) y[J] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4 * NB; ++k)
+#pragma unroll
+                for (int J = 0; J < NB; ++J)
+                    y[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(b.v[u][k], Ms[(4 * k + hi) * NPAD + 16 * J + lo], y[J],
+                                                               0, 0, 0);
+        } else {
+#pragma unroll
+            for (int J = 0; J < NB; ++J)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[J][q] = b.v[u][4 * J + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (NB == 1) {
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[0][q], y[0][q], acc[q], 0, 0, 0);
+            } else {
+                int t = 0;
+#pragma unroll
+                for (int I = 0; I < NB; ++I)
+#pragma unroll
+                    for (int J = I; J < NB; ++J, ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(y[I][q], y[J][q], acc[t], 0, 0, 0);
+            }
+        }
     }
-    if (g == 0 && i < n) {
-        double* out = Cpart + w * (int64_t)n * n + (int64_t)i * n;
-#pragma unroll
-        for (int c = 0; c < NP; ++c)
-            if (c < n) out[c] = acc[c];
+}
+
+// Rows [r_begin, r_end) of one wavefront, in stages of U 16-row blocks,
+// double-buffered: the loads of stage s+1 are issued before stage s is
+// multiplied (the last full stage is requested twice, so every iteration
+// issues the same loads).  The partial stage at the end loads guarded.
+template <int NB, bool HAS_M, bool GUARD>
+__device__ __forceinline__ void gram_range(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                           int64_t r_end, const double* __restrict__ Ms,
+                                           f64x4 (&acc)[gram_accs<NB>()], int lo, int hi) {
+    constexpr int64_t STAGE = 16 * gram_sub_blocks<NB>();
+    const int64_t nfull = (r_end - r_begin) / STAGE;
+    if (nfull > 0) {
+        const int64_t last = r_begin + (nfull - 1) * STAGE;   // start of the last full stage
+        GramStage<NB> ba, bb;
+        gram_load_stage<NB, HAS_M, GUARD>(ba, X, n, ldx, r_begin, r_end, lo, hi);
+        for (int64_t r0 = r_begin;;) {
+            gram_load_stage<NB, HAS_M, GUARD>(bb, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
+            gram_stage<NB, HAS_M>(ba, Ms, acc, lo, hi);
+            r0 += STAGE;
+            if (r0 > last) break;
+            gram_load_stage<NB, HAS_M, GUARD>(ba, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
+            gram_stage<NB, HAS_M>(bb, Ms, acc, lo, hi);
+            r0 += STAGE;
+            if (r0 > last) break;
+        }
     }
+    const int64_t rt = r_begin + nfull * STAGE;
+    if (rt < r_end) {
+        GramStage<NB> bt;
+        gram_load_stage<NB, HAS_M, true>(bt, X, n, ldx, rt, r_end, lo, hi);
+        gram_stage<NB, HAS_M>(bt, Ms, acc, lo, hi);
+    }
+}
+
+// One wavefront per contiguous row range (gram_range).
+template <int NB, bool HAS_M>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+gram_mfma_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                 int64_t nwaves, const double* __restrict__ M, double* __restrict__ Cpart) {
+    constexpr int NPAD = 16 * NB;
+    constexpr int NA = gram_accs<NB>();
+    __shared__ double Ms[HAS_M ? NPAD * NPAD : 1];
+    if constexpr (HAS_M) {
+        for (int e = threadIdx.x; e < NPAD * NPAD; e += blockDim.x) {
+            const int k = e / NPAD, c = e % NPAD;
+            Ms[e] = (k < n && c < n) ? M[(int64_t)k * n + c] : 0.0;
+        }
+        __syncthreads();
+    }
+    const int lane = lane_id();
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wib;
+    if (w >= nwaves) return;
+    const int lo = lane & 15, hi = lane >> 4;
+    f64x4 acc[NA];
+#pragma unroll
+    for (int t = 0; t < NA; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    if (n == NPAD) gram_range<NB, HAS_M, false>(X, n, ldx, r_begin, r_end, Ms, acc, lo, hi);
+    else gram_range<NB, HAS_M, true>(X, n, ldx, r_begin, r_end, Ms, acc, lo, hi);
+    if constexpr (NB == 1) acc[0] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    // tile (I, J): this lane holds C[16I + 4v + hi][16J + lo]; the lower tiles
+    // are the transposes of the upper ones
+    double* out = Cpart + w * (int64_t)n * n;
+    int t = 0;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = I; J < NB; ++J, ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + 4 * v + hi, j = 16 * J + lo;
+                if (i < n && j < n) {
+                    out[(int64_t)i * n + j] = acc[t][v];
+                    if (I != J) out[(int64_t)j * n + i] = acc[t][v];
+                }
+            }
 }
 
 // Row layout for n <= 8: each lane holds RPL full rows of a 64*RPL-row panel
@@ -183,47 +304,64 @@ gram_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     }
 }
 
-// C = sum over w < k of Cpart[w] (n x n), in a fixed order: each of the
-// PARTS threads of an entry sums a contiguous range of w sequentially, and
-// the PARTS subtotals are added pairwise in LDS.
+// C = sum over w < k of Cpart[w] (n x n), in a fixed order.  A workgroup
+// takes 16 entries; the 16 threads of an entry take the partials w = p,
+// p + 16, ... (p = thread's part) with four running sums each, so many loads
+// are in flight, and the parts are then added pairwise in LDS.  The order
+// depends only on k, so the result is reproducible bit for bit.
+constexpr int kSumParts = 16;
+constexpr int kSumEntries = 256 / kSumParts;
+
 __global__ void __launch_bounds__(256)
 gram_sum_kernel(const double* __restrict__ Cpart, int64_t k, int n, double* __restrict__ C) {
-    __shared__ double sub[256];
+    __shared__ double sub[kSumParts][kSumEntries];
     const int nn = n * n;
-    const int parts = 256 / 64;  // 4 threads per entry, 64 entries per block
-    const int e = blockIdx.x * 64 + (threadIdx.x % 64);
-    const int part = threadIdx.x / 64;
-    const int64_t chunk = ceil_div(k, parts);
-    const int64_t w0 = part * chunk;
-    const int64_t w1 = (w0 + chunk < k) ? w0 + chunk : k;
-    double s = 0.0;
-    if (e < nn)
-        for (int64_t w = w0; w < w1; ++w) s += Cpart[w * nn + e];
-    sub[threadIdx.x] = s;
-    __syncthreads();
-    if (part == 0 && e < nn) {
-        double a = sub[threadIdx.x] + sub[threadIdx.x + 64];
-        double b = sub[threadIdx.x + 128] + sub[threadIdx.x + 192];
-        C[e] = a + b;
+    const int j = threadIdx.x % kSumEntries;
+    const int p = threadIdx.x / kSumEntries;
+    const int e = blockIdx.x * kSumEntries + j;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < nn) {
+        const double* src = Cpart + e;
+        int64_t w = p;
+        for (; w + 3 * kSumParts < k; w += 4 * kSumParts) {
+            s0 += src[w * nn];
+            s1 += src[(w + kSumParts) * nn];
+            s2 += src[(w + 2 * kSumParts) * nn];
+            s3 += src[(w + 3 * kSumParts) * nn];
+        }
+        for (; w < k; w += kSumParts) s0 += src[w * nn];
     }
+    sub[p][j] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    for (int h = kSumParts / 2; h > 0; h /= 2) {
+        if (p < h) sub[p][j] += sub[p + h][j];
+        __syncthreads();
+    }
+    if (p == 0 && e < nn) C[e] = sub[0][j];
 }
 
 template <int NP, bool HAS_M>
-hipError_t launch_gram_t(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                         const double* M, double* Cpart, hipStream_t s) {
-    if constexpr (NP <= 8) {
-        // with the fused multiply, half the rows per lane leave room for y = x M
-        constexpr int RPL = HAS_M ? (NP >= 32 ? 1 : 32 / NP) : 64 / NP;
-        hipLaunchKernelGGL((gram_rows_kernel<NP, RPL, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s,
-                           X, m, n, ldx, rpw, nw, M, Cpart);
-    } else {
-        hipLaunchKernelGGL((gram_kernel<NP, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n,
-                           ldx, rpw, nw, M, Cpart);
-    }
+hipError_t launch_gram_rows(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
+                            const double* M, double* Cpart, hipStream_t s) {
+    // with the fused multiply, half the rows per lane leave room for y = x M
+    constexpr int RPL = HAS_M ? 32 / NP : 64 / NP;
+    hipLaunchKernelGGL((gram_rows_kernel<NP, RPL, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n,
+                       ldx, rpw, nw, M, Cpart);
     return hipGetLastError();
 }
 
+template <int NB, bool HAS_M>
+hipError_t launch_gram_mfma(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
+                            const double* M, double* Cpart, hipStream_t s) {
+    hipLaunchKernelGGL((gram_mfma_kernel<NB, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n, ldx,
+                       rpw, nw, M, Cpart);
+    return hipGetLastError();
+}
+
+// Kernel width: n <= 8 padded to a power of two (row layout); wider n to
+// whole blocks of 16 columns (matrix cores).
 int gram_npad(int64_t n) {
+    if (n > 8) return (int)ceil_div(n, 16) * 16;
     int np = 1;
     while (np < n) np <<= 1;
     return np;
@@ -234,7 +372,7 @@ int gram_npad(int64_t n) {
 GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus) {
     GramPlan p;
     p.npad = gram_npad(n);
-    const int64_t slab = p.npad <= 8 ? (int64_t)kWave * (64 / p.npad) : 512 / p.npad;
+    const int64_t slab = p.npad <= 8 ? (int64_t)kWave * (64 / p.npad) : 64;
     const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * 8;
     int64_t rpw = ceil_div(m > 0 ? m : 1, max_waves);
     rpw = ceil_div(rpw, slab) * slab;
@@ -250,19 +388,28 @@ hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const
     hipError_t e = hipErrorInvalidValue;
     timing_begin(kTimeGram, s);
     const bool hm = (M != nullptr);
+    const int64_t rpw = plan.rows_per_wave, k = plan.k;
     switch (plan.npad) {
-#define QLESS_GCASE(NP)                                                                              \
-    case NP:                                                                                         \
-        e = hm ? launch_gram_t<NP, true>(X, m, ni, ldx, plan.rows_per_wave, plan.k, M, Cpart, s)     \
-               : launch_gram_t<NP, false>(X, m, ni, ldx, plan.rows_per_wave, plan.k, M, Cpart, s);   \
+#define QLESS_GROWS(NP)                                                                           \
+    case NP:                                                                                      \
+        e = hm ? launch_gram_rows<NP, true>(X, m, ni, ldx, rpw, k, M, Cpart, s)                   \
+               : launch_gram_rows<NP, false>(X, m, ni, ldx, rpw, k, M, Cpart, s);                 \
         break;
-        QLESS_GCASE(1) QLESS_GCASE(2) QLESS_GCASE(4) QLESS_GCASE(8) QLESS_GCASE(16) QLESS_GCASE(32) QLESS_GCASE(64)
-#undef QLESS_GCASE
+#define QLESS_GMFMA(NB)                                                                           \
+    case 16 * NB:                                                                                 \
+        e = hm ? launch_gram_mfma<NB, true>(X, m, ni, ldx, rpw, k, M, Cpart, s)                   \
+               : launch_gram_mfma<NB, false>(X, m, ni, ldx, rpw, k, M, Cpart, s);                 \
+        break;
+        QLESS_GROWS(1) QLESS_GROWS(2) QLESS_GROWS(4) QLESS_GROWS(8)
+        QLESS_GMFMA(1) QLESS_GMFMA(2) QLESS_GMFMA(3) QLESS_GMFMA(4)
+#undef QLESS_GROWS
+#undef QLESS_GMFMA
         default: break;
     }
     timing_end(kTimeGram, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)ceil_div(n * n, 64)), dim3(256), 0, s, Cpart, plan.k, ni, C);
+    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)ceil_div(n * n, kSumEntries)), dim3(256), 0, s, Cpart, plan.k, ni,
+                       C);
     return hipGetLastError();
 }
 

@@ -231,7 +231,7 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
 
 // Plan of a Gram pass: wavefront count and rows per wavefront.
 struct GramPlan {
-    int npad = 0;              // padded column count (power of two)
+    int npad = 0;              // kernel width: power of two up to 8, else a multiple of 16
     int64_t rows_per_wave = 0;
     int64_t k = 0;             // wavefronts = partial Gram matrices
     size_t part_bytes = 0;     // bytes of the k partials
