@@ -157,7 +157,10 @@ int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
  * per tree wavefront (0 = default: one panel of stacked rows for n <= 16,
  * else 16; explicit values 2..256), rows_per_lane = panel rows
  * per lane, one of the compiled variants for that n (0 = default;
- * QLESS_ERR_UNSUPPORTED if no such variant).  Process-wide, not thread-safe;
+ * QLESS_ERR_UNSUPPORTED if no such variant).  For n padding to 32, 48 or 64
+ * columns, rows_per_lane = 1 selects the blocked fold on the FP64 matrix
+ * cores (64-row panels, 16-column blocks in compact WY form; the same
+ * reflectors, sums regrouped).  Process-wide, not thread-safe;
  * query qless_workspace_bytes after changing it.  qless_tune_get returns the
  * values in effect (defaults resolved).
  */

@@ -2,7 +2,8 @@
 
 For each column count n it times ``qless_tsqr_r`` on a synthetic m x n
 matrix over a small grid of
-  * rows_per_lane  -- panel height (the compiled variants for that n),
+  * rows_per_lane  -- panel height (the compiled variants for that n; for
+                      n > 16, 1 selects the matrix-core blocked fold),
   * waves_per_cu   -- stage-1 row blocks per compute unit,
   * fan_in         -- triangles combined per tree wavefront,
 keeps the fastest, and stores the table in a JSON cache keyed by GPU
@@ -47,8 +48,9 @@ def rows_per_lane_variants(n: int) -> list[int]:
     q.qless_tune_set(n, 0, 0, 0)
     default = q.qless_tune_get(n)["rows_per_lane"]
     out = [default]
-    for cand in (default // 2, default * 2):
-        if cand >= 1:
+    # 1 for n > 16: the matrix-core blocked fold (64-row panels)
+    for cand in (default // 2, default * 2) + ((1,) if n > 16 else ()):
+        if cand >= 1 and cand not in out:
             try:
                 q.qless_tune_set(n, 0, 0, cand)
                 out.append(cand)

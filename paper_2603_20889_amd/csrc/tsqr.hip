@@ -18,7 +18,7 @@ namespace qless {
     X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5)              \
     X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)                     \
     X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(16, 2) X(32, 8) X(64, 4)  \
-    X(16, 3)
+    X(16, 3) X(32, 1) X(48, 1) X(64, 1)
 QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
 // One-workgroup last tree level, compiled for n <= 16 (launch_tree_np<NP>_r<RPL>).
@@ -62,14 +62,25 @@ const TreeEntry kTrees[] = {
 #undef QLESS_TREE_ENTRY
 };
 
-// Wavefronts per workgroup of the fold kernel (tsqr_detail::waves_per_block).
-constexpr int waves_per_block_for(int np) {
-    return ((np * (np + 1) / 2 + np) * 8 * 4 <= 65536) ? 4 : 2;
+// Matrix-core instance (tsqr_detail::mf_instance) and wavefronts per
+// workgroup of the fold kernel (tsqr_detail::waves_per_block).
+constexpr bool mf_instance_for(int np, int rpl) { return np > 16 && rpl == 1; }
+constexpr int waves_per_block_for(int np, int rpl) {
+    return (mf_instance_for(np, rpl) || (np * (np + 1) / 2 + np) * 8 * 4 > 65536) ? 2 : 4;
 }
-static_assert(waves_per_block_for(8) == tsqr_detail::waves_per_block<8>() &&
-                  waves_per_block_for(56) == tsqr_detail::waves_per_block<56>() &&
-                  waves_per_block_for(64) == tsqr_detail::waves_per_block<64>(),
+static_assert(waves_per_block_for(8, 4) == tsqr_detail::waves_per_block<8, 4>() &&
+                  waves_per_block_for(56, 8) == tsqr_detail::waves_per_block<56, 8>() &&
+                  waves_per_block_for(64, 7) == tsqr_detail::waves_per_block<64, 7>() &&
+                  waves_per_block_for(32, 1) == tsqr_detail::waves_per_block<32, 1>(),
               "host and device workgroup sizes differ");
+// Rows of one panel of an instance (the unit rows_per_wave is rounded to).
+constexpr int64_t panel_rows_for(int np, int rpl) {
+    return (int64_t)(np <= 16 || mf_instance_for(np, rpl) ? kWave : tsqr_detail::kRG2) * rpl;
+}
+static_assert(panel_rows_for(32, 1) == tsqr_detail::panel_rows<32, 1>() &&
+                  panel_rows_for(32, 16) == tsqr_detail::panel_rows<32, 16>() &&
+                  panel_rows_for(8, 4) == tsqr_detail::panel_rows<8, 4>(),
+              "host and device panel heights differ");
 
 TreeFn find_tree(int np, int rpl) {
     for (const TreeEntry& t : kTrees)
@@ -132,7 +143,7 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     const Instance* in = find_instance(npad_for(n), t.rpl);
     p.npad = in->npad;
     p.rows_per_lane = in->rpl;
-    const int64_t panel = (int64_t)(in->npad <= 16 ? kWave : tsqr_detail::kRG2) * in->rpl;
+    const int64_t panel = panel_rows_for(in->npad, in->rpl);
     const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * (t.waves_per_cu ? t.waves_per_cu : 8);
     int64_t rpw = ceil_div(m > 0 ? m : 1, max_waves);
     rpw = ceil_div(rpw, panel) * panel;
@@ -141,7 +152,7 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     if (m <= 4 * panel) rpw = ceil_div(m > 0 ? m : 1, panel) * panel;
     p.rows_per_wave = rpw;
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
-    p.wpb = waves_per_block_for(in->npad);
+    p.wpb = waves_per_block_for(in->npad, in->rpl);
     // Each launch leaves one triangle per workgroup.  Tree for n <= 16:
     // fan-in levels of one panel per wavefront (fan_in = panel / n) until the
     // remaining triangles fit one panel per wavefront of the one-workgroup

@@ -113,10 +113,15 @@ struct LaneOrigins {
 // written back to LDS, and the coefficients are shared through LDS
 // broadcast reads.  The reflector scalars (norm, beta, gamma) are
 // wave-uniform.
-template <int NP, int RPL, int J>
+// With REC, the pivot entry u0 and gamma of every step's reflector are
+// written to rec[J] and rec[NP + J] (0 and 0 for a column left as it is):
+// the blocked fold builds its block reflector from them.  Rw is a packed
+// triangle of row width W (the NP x NP diagonal block of a wider triangle
+// when W > NP: row J of the block starts at tri_row<W>(J)).
+template <int NP, int RPL, int J, bool REC = false, int W = NP>
 struct FoldStep {
     __device__ static __forceinline__ void run(double (&x)[RPL][NP], double* __restrict__ Rw, double* __restrict__ Cw,
-                                               const LaneOrigins<NP>& org, int lane) {
+                                               const LaneOrigins<NP>& org, int lane, double* rec = nullptr) {
         if constexpr (J < NP) {
             constexpr int K = NP - J;
             double p[K];
@@ -127,16 +132,28 @@ struct FoldStep {
                 for (int i = 0; i < RPL; ++i) s = fma(x[i][J], x[i][J + t], s);
                 p[t] = s;
             }
-            const double alpha = Rw[tri_row<NP>(J)];
+            const double alpha = Rw[tri_row<W>(J)];
             red_stages<K, 0>(p, lane);                  // p[0]: total of value v in this lane
             const int v = org.template get<K>();
-            const double r = Rw[tri_row<NP>(J) + v];
+            const double r = Rw[tri_row<W>(J) + v];
             const double s = readlane_f64(p[0], red_locate(K, 0));
+            if constexpr (REC) {
+                if (s == 0.0 && lane == 0) {
+                    rec[J] = 0.0;
+                    rec[NP + J] = 0.0;
+                }
+            }
             if (s != 0.0) {
                 double beta, u0, gamma;
                 reflector_scalars(alpha, s, beta, u0, gamma);
+                if constexpr (REC) {
+                    if (lane == 0) {
+                        rec[J] = u0;
+                        rec[NP + J] = gamma;
+                    }
+                }
                 const double coef = gamma * fma(u0, r, p[0]);   // gamma * (u^T column J+v)
-                Rw[tri_row<NP>(J) + v] = (v == 0) ? beta : fma(-coef, u0, r);
+                Rw[tri_row<W>(J) + v] = (v == 0) ? beta : fma(-coef, u0, r);
                 if constexpr (K > 1) {
                     Cw[v] = coef;                        // every holder of v writes the same value
                     __builtin_amdgcn_wave_barrier();
@@ -149,7 +166,7 @@ struct FoldStep {
                         for (int i = 0; i < RPL; ++i) x[i][J + t] = fma(-c[t], x[i][J], x[i][J + t]);
                 }
             }
-            FoldStep<NP, RPL, J + 1>::run(x, Rw, Cw, org, lane);
+            FoldStep<NP, RPL, J + 1, REC, W>::run(x, Rw, Cw, org, lane, rec);
         }
     }
 };
@@ -197,9 +214,20 @@ constexpr bool lane_private() {
     return NP <= 8;
 }
 
-template <int NP>
+// Instances for n > 16 with one row per lane are the matrix-core blocked
+// fold (64-row panels, fold_rows_mfma); the column-group layout has 8 rows
+// per panel and row group, so it never uses RPL = 1.
+template <int NP, int RPL>
+constexpr bool mf_instance() {
+    return NP > 16 && RPL == 1;
+}
+
+// Wavefronts per workgroup of the fold kernel: 4, or 2 where four packed
+// triangles would take more than 64 KB of LDS.  The matrix-core instances
+// keep 2, since each wavefront also holds transposes in LDS.
+template <int NP, int RPL>
 constexpr int waves_per_block() {
-    return ((tri_size<NP>() + NP) * 8 * 4 <= 65536) ? 4 : 2;
+    return (mf_instance<NP, RPL>() || (tri_size<NP>() + NP) * 8 * 4 > 65536) ? 2 : 4;
 }
 
 // Panel loads for the layout of n <= 16: lane l gets rows base + l + 64 i
@@ -604,18 +632,196 @@ __device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n
     }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked fold on the FP64 matrix cores for n = 32, 48, 64 (the instances
+// with one row per lane; v_mfma_f64_16x16x4f64).  A panel of 64 rows W is
+// held in registers as NB = NP/16 column blocks in the matrix-core operand
+// layout: register c of lane l of block K holds W[4c + l/16][16K + l%16].
+// Block J is folded into the running R column by column -- the reflectors
+// of the unblocked fold, with their pivot entries u0_j and gamma_j recorded
+// -- after a transpose through LDS to one row per lane.  Its 16 reflectors
+// H_j = I - gamma_j u_j u_j^T then act on the later blocks at once in
+// compact WY form (forward, columnwise: H_0 H_1 ... H_15 = I - U T U^T with
+// T_jj = gamma_j and T_{0:j,j} = -gamma_j T_{0:j,0:j} U_{:,0:j}^T u_j).  U
+// stacks diag(u0) on the R rows of block J over V, the 64 x 16 reflector
+// part in W, so U^T U = diag(u0^2) + V^T V, and only its strictly upper
+// part, that of V^T V, enters T.  For a later block K, with C = [R_{J,K}; W_K]:
+//   S  = U^T C = diag(u0) R_{J,K} + V^T W_K     (16 matrix-core steps)
+//   S' = T^T S                                  (4)
+//   R_{J,K} -= diag(u0) S',  W_K -= V S'        (16)
+// which is applying the 16 reflectors in turn with the sums regrouped.
+//
+// Per-wavefront LDS scratch (doubles): the 64 x 16 transpose buffer (row
+// stride 17), V^T V (16 x 16), T (stride 17), the recorded u0 and gamma,
+// and the coefficient exchange of the column fold.
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfVs = 17;                       // row stride of the transpose buffer and of T
+constexpr int kMfV = 0;                         // 64 x 16 (stride 17)
+constexpr int kMfY = kMfV + 64 * kMfVs;         // 16 x 16
+constexpr int kMfT = kMfY + 256;                // 16 x 16 (stride 17)
+constexpr int kMfRec = kMfT + 16 * kMfVs;       // u0[16], gamma[16]
+constexpr int kMfCw = kMfRec + 32;              // 16
+constexpr int kMfScratch = kMfCw + 16;
+
+// Block KB (columns 16KB..16KB+15) of the 64-row panel at row `base`, in
+// the operand layout; rows >= r_end and columns >= n read as zero.
+template <int KB>
+__device__ __forceinline__ void mf_load_block(double (&gk)[16], const double* __restrict__ X, int n, int64_t ldx,
+                                              int64_t base, int64_t r_end, bool fast, int lane) {
+    const int lo = lane & 15, hi = lane >> 4;
+    if (fast && base + 64 <= r_end) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+        const int vo = (int)((hi * ldx + 16 * KB + lo) * 8);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            gk[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, (int)(4 * c * ldx * 8), 0));
+    } else {
+        const int col = 16 * KB + lo;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int64_t row = base + 4 * c + hi;
+            gk[c] = (row < r_end && col < n) ? X[row * ldx + col] : 0.0;
+        }
+    }
+}
+
+template <int NP, int KB>
+__device__ __forceinline__ void mf_load_panel(double (&g)[NP / 16][16], const double* __restrict__ X, int n,
+                                              int64_t ldx, int64_t base, int64_t r_end, bool fast, int lane) {
+    if constexpr (KB < NP / 16) {
+        mf_load_block<KB>(g[KB], X, n, ldx, base, r_end, fast, lane);
+        mf_load_panel<NP, KB + 1>(g, X, n, ldx, base, r_end, fast, lane);
+    }
+}
+
+// Block JB of the panel in g: fold it into R (Rw, packed NP x NP), apply its
+// reflectors to blocks JB+1.., and start loading block JB of the next panel
+// (row `next`) into the registers it frees.
+template <int NP, int JB>
+__device__ __forceinline__ void mf_fold_block(double (&g)[NP / 16][16], double* __restrict__ Rw,
+                                              double* __restrict__ scr, const LaneOrigins<16>& org, int lane,
+                                              const double* __restrict__ X, int n, int64_t ldx, int64_t next,
+                                              int64_t r_end, bool fast) {
+    constexpr int NB = NP / 16;
+    const int lo = lane & 15, hi = lane >> 4;
+    double* __restrict__ Vt = scr + kMfV;
+    double* __restrict__ rec = scr + kMfRec;
+    // block JB to one row per lane
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Vt[(4 * c + hi) * kMfVs + lo] = g[JB][c];
+    double x[1][16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[0][t] = Vt[lane * kMfVs + t];
+    if (next < r_end) mf_load_block<JB>(g[JB], X, n, ldx, next, r_end, fast, lane);
+    // column fold of the diagonal block (rows 16JB.. of R), reflectors recorded
+    FoldStep<16, 1, 0, true, NP - 16 * JB>::run(x, Rw + tri_row<NP>(16 * JB), scr + kMfCw, org, lane, rec);
+    if constexpr (JB + 1 < NB) {
+        // x[0][t] = V[lane][t]: the reflector parts in W
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Vt[lane * kMfVs + t] = x[0][t];
+        double vg[16];                       // V in the operand layout
+#pragma unroll
+        for (int c = 0; c < 16; ++c) vg[c] = Vt[(4 * c + hi) * kMfVs + lo];
+        // Y = V^T V
+        mf64x4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 16; ++c) y = __builtin_amdgcn_mfma_f64_16x16x4f64(vg[c], vg[c], y, 0, 0, 0);
+        double* __restrict__ Y = scr + kMfY;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Y[(4 * v + hi) * 16 + lo] = y[v];
+        // T, one row per lane (row i = lane % 16): T_ii = gamma_i and, for
+        // j > i, T_ij = -gamma_j sum_{i<=k<j} T_ik Y_kj
+        double tr[16];
+        const double gi = rec[16 + lo];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tr[k] = (k == lo) ? gi : 0.0;
+#pragma unroll
+        for (int j = 1; j < 16; ++j) {
+            asm volatile("" ::: "memory");   // read each column of Y where it is used
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < j; ++k) a = fma(tr[k], Y[k * 16 + j], a);
+            const double gj = rec[16 + j];
+            if (j > lo) tr[j] = -gj * a;
+        }
+        double* __restrict__ T = scr + kMfT;
+        if (hi == 0) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) T[lo * kMfVs + j] = tr[j];
+        }
+        double ta[4];                        // T^T in the A layout
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ta[c] = T[(4 * c + hi) * kMfVs + lo];
+        double va[4][4];                     // -V in the A layout, row tile u
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) va[u][c] = -Vt[(16 * u + lo) * kMfVs + 4 * c + hi];
+        double u0r[4];                       // u0 of the R row this lane's S entries sit on
+#pragma unroll
+        for (int v = 0; v < 4; ++v) u0r[v] = rec[4 * v + hi];
+#pragma unroll
+        for (int K = JB + 1; K < NB; ++K) {
+            int ri[4];
+            mf64x4 s;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * JB + 4 * v + hi;
+                ri[v] = tri_row<NP>(row) + 16 * K + lo - row;
+                s[v] = u0r[v] * Rw[ri[v]];
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) s = __builtin_amdgcn_mfma_f64_16x16x4f64(vg[c], g[K][c], s, 0, 0, 0);
+            mf64x4 sp = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sp = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[c], s[c], sp, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Rw[ri[v]] = fma(-u0r[v], sp[v], Rw[ri[v]]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                mf64x4 acc = {g[K][4 * u], g[K][4 * u + 1], g[K][4 * u + 2], g[K][4 * u + 3]};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][c], sp[c], acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) g[K][4 * u + v] = acc[v];
+            }
+        }
+        mf_fold_block<NP, JB + 1>(g, Rw, scr, org, lane, X, n, ldx, next, r_end, fast);
+    }
+}
+
+// Fold rows [r_begin, r_end) of X (n <= NP columns) into Rw, 64 rows at a
+// time; the loads of each panel overlap the work on the one before.
+template <int NP>
+__device__ __forceinline__ void fold_rows_mfma(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                               int64_t r_end, double* __restrict__ Rw, double* __restrict__ scr,
+                                               int lane) {
+    static_assert(NP % 16 == 0, "the matrix-core fold works on 16-column blocks");
+    if (r_begin >= r_end) return;
+    LaneOrigins<16> org;
+    org.init(lane);
+    const bool fast = n == NP && (int64_t)64 * ldx * 8 < 0x7FFFFFFF;
+    double g[NP / 16][16];
+    mf_load_panel<NP, 0>(g, X, n, ldx, r_begin, r_end, fast, lane);
+    for (int64_t base = r_begin; base < r_end; base += 64)
+        mf_fold_block<NP, 0>(g, Rw, scr, org, lane, X, n, ldx, base + 64, r_end, fast);
+}
+
 template <int NP, int RPL>
 __device__ __forceinline__ void fold_rows(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
                                           int64_t r_end, double* __restrict__ Rw, int lane,
                                           double* stage = nullptr) {
-    if constexpr (NP <= 16) fold_rows_1d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane, stage);
+    if constexpr (mf_instance<NP, RPL>()) fold_rows_mfma<NP>(X, n, ldx, r_begin, r_end, Rw, stage, lane);
+    else if constexpr (NP <= 16) fold_rows_1d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane, stage);
     else fold_rows_2d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
 }
 
 // Rows of a panel for an instance (the unit rows_per_wave is rounded to).
 template <int NP, int RPL>
 constexpr int64_t panel_rows() {
-    return (int64_t)(NP <= 16 ? kWave : kRG2) * RPL;
+    return (int64_t)(NP <= 16 || mf_instance<NP, RPL>() ? kWave : kRG2) * RPL;
 }
 
 template <int NP>
@@ -671,14 +877,15 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
             FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
         }
     } else {
+        constexpr int CR = mf_instance<NP, RPL>() ? 4 : RPL;   // matrix-core instances combine in this layout
         const int rg = lane / kG2, cg = lane % kG2;
-        for (int base = 0; base < rows; base += kRG2 * RPL) {
-            double x[RPL][NP / kG2];
+        for (int base = 0; base < rows; base += kRG2 * CR) {
+            double x[CR][NP / kG2];
 #pragma unroll
-            for (int i = 0; i < RPL; ++i)
+            for (int i = 0; i < CR; ++i)
 #pragma unroll
                 for (int u = 0; u < NP / kG2; ++u) x[i][u] = value(base + rg + kRG2 * i, cg + kG2 * u);
-            FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
+            FoldStep2D<NP, CR, 0>::run(x, Rw, lane);
         }
     }
 }
@@ -692,12 +899,12 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
 // Y + blockIdx.x*ystride (leading dimension ldy).  With normalise (a single
 // workgroup, the final R), rows of a negative diagonal are negated.
 template <int NP, int RPL>
-__global__ void __launch_bounds__(64 * waves_per_block<NP>()) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__((64 * waves_per_block<NP, RPL>())) __attribute__((amdgpu_waves_per_eu(2)))
 tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
                  int64_t nwaves, double* __restrict__ Y, int64_t ldy, int64_t ystride, int normalise) {
-    constexpr int WPB = waves_per_block<NP>();
+    constexpr int WPB = waves_per_block<NP, RPL>();
     constexpr int STRIDE = tri_size<NP>() + NP;
-    constexpr int STAGE = staged_instance<NP, RPL>() ? kWave * RPL * NP : 2;
+    constexpr int STAGE = mf_instance<NP, RPL>() ? kMfScratch : staged_instance<NP, RPL>() ? kWave * RPL * NP : 2;
     __shared__ double Rsh[WPB][STRIDE];
     __shared__ __attribute__((aligned(16))) double stage[WPB][STAGE];
     __shared__ int arrivals;
@@ -713,7 +920,8 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     zero_r<NP>(Rw, lane);
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
-    fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane, staged_instance<NP, RPL>() ? stage[wib] : nullptr);
+    fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane,
+                       (mf_instance<NP, RPL>() || staged_instance<NP, RPL>()) ? stage[wib] : nullptr);
     if (nvalid > 1) {
         int old = 0;
         if (lane == 0) old = __hip_atomic_fetch_add(&arrivals, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -728,7 +936,7 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
 template <int NP, int RPL>
 hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave, int64_t nwaves,
                        double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t stream) {
-    constexpr int WPB = waves_per_block<NP>();
+    constexpr int WPB = waves_per_block<NP, RPL>();
     const int64_t blocks = ceil_div(nwaves, WPB);
     hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, X, m, n, ldx,
                        rows_per_wave, nwaves, Y, ldy, ystride, normalise);

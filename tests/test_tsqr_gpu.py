@@ -199,3 +199,42 @@ def test_running_update(gpu, n, chunks):
         lo += c
     torch.cuda.synchronize(gpu)
     check(X, R.cpu().numpy())
+
+
+# Matrix-core blocked fold (the instances for n in (16, 64] with one row per
+# lane: 64-row panels, 16-column blocks applied in compact WY form), for the
+# exact widths and ragged ones (zero-padded columns), with one wavefront per
+# CU so that stage 1, the workgroup combine and a tree of several levels all
+# run on it.
+@pytest.mark.parametrize("n", [32, 30, 25, 48, 45, 64, 61])
+def test_matrix_core_instance(gpu, n):
+    cus = torch.cuda.get_device_properties(gpu).multi_processor_count
+    m = cus * (4 * 64 + 32) + 333
+    print("case matrix-core instance n=%d m=%d" % (n, m), flush=True)
+    X = wl.gaussian(m, n, seed=4000 + n)
+    q.qless_tune_set(n, 1, 0, 1)
+    try:
+        R = run(X, gpu)
+    finally:
+        q.qless_tune_set(n, 0, 0, 0)
+    check(X, R)
+
+
+@pytest.mark.parametrize("n,k,m", [(32, 4, 60_000), (64, 4, 60_000), (48, 8, 60_000), (64, 0, 129),
+                                   (32, 4, 65), (64, 4, 64)])
+def test_matrix_core_known_r(gpu, n, k, m):
+    """Known-answer inputs X = Q0 R0 (singular values 1 .. 10^-k) through the
+    matrix-core fold, including single-panel and ragged-panel heights."""
+    print("case matrix-core known-R n=%d k=%d m=%d" % (n, k, m), flush=True)
+    X, R0 = wl.known_r(m, n, wl.logspace_sigma(n, k), seed=950 + n + k)
+    q.qless_tune_set(n, 0, 0, 1)
+    try:
+        R = run(X, gpu)
+    finally:
+        q.qless_tune_set(n, 0, 0, 0)
+    if k <= 4:
+        check(X, R)
+        assert oracle.rel_err_r(R, R0) <= E_R
+    else:
+        assert oracle.gram_residual(X, R) <= E_G
+        assert oracle.rel_err_r(R, oracle.householder_r(X)) <= 1e-10

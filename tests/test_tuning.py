@@ -46,6 +46,23 @@ def test_tuning_changes_the_plan():
 def test_variants_listed():
     assert autotune.rows_per_lane_variants(8) == [4, 8]
     assert autotune.rows_per_lane_variants(16)[0] == 4
+    # n > 16: the column-group variants and the matrix-core fold (one row per lane)
+    assert autotune.rows_per_lane_variants(32) == [16, 8, 1]
+    assert autotune.rows_per_lane_variants(64) == [7, 1]
+    assert autotune.rows_per_lane_variants(24) == [21]
+
+
+def test_matrix_core_instance_selection():
+    """n in (16, 64] with rows_per_lane 1 selects the matrix-core fold; the
+    widths that pad to 24, 40 or 56 columns have no such instance."""
+    q.qless_tune_set(32, 8, 0, 1)
+    assert q.qless_tune_get(32)["rows_per_lane"] == 1
+    q.qless_tune_set(61, 8, 0, 1)
+    assert q.qless_tune_get(61)["rows_per_lane"] == 1
+    for n in (24, 40, 56):
+        with pytest.raises(q.QlessError) as e:
+            q.qless_tune_set(n, 8, 0, 1)
+        assert e.value.status == q.QLESS_ERR_UNSUPPORTED
 
 
 def test_apply_and_cache_file(tmp_path, monkeypatch):
