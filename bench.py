@@ -106,15 +106,22 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--ns", type=str, default="1,2,4,8,16,32,64",
                     help="column counts of the m = 2^25 sweep")
+    ap.add_argument("--sweep-ks", type=str, default="0,4,8",
+                    help="condition exponents k of the sweep (sigma down to 10^-k); timing runs at k = 4")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=300)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) for HBM-counter calibration")
+    ap.add_argument("--tune", type=str, default="",
+                    help="launch-parameter overrides n:rows_per_lane[:waves_per_cu[:fan_in]],... "
+                         "(qless_tune_set) applied before any timing, e.g. 32:1,64:1 for the "
+                         "matrix-core fold")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rows would shard across GPUs with one n x n all-gather; see DESIGN.md).",
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(rows would shard across GPUs, each GPU folding its rows to one n x n "
+              "triangle, with one gather of the triangles and a last fold).",
               file=sys.stderr)
         return 2
 
@@ -129,6 +136,13 @@ def main() -> int:
     q.load()
     m, n = args.m, args.n
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    tuned = {}
+    for item in filter(None, args.tune.split(",")):
+        f = [int(v) for v in item.split(":")] + [0, 0]
+        q.qless_tune_set(f[0], f[2], f[3], f[1])
+        tuned[f[0]] = q.qless_tune_get(f[0])
+    if tuned:
+        log("tuning overrides: %s" % tuned)
 
     log("generating X = Q0 R0 (%d x %d, kappa 1e4) on the GPU" % (m, n))
     X, R0 = wl.config2(m=m, n=n, device=dev)
@@ -180,6 +194,7 @@ def main() -> int:
                      "algorithmic_bytes_per_launch": nbytes},
         "accuracy": {"e_R_vs_R0": e_r},
         "kernel_hash": kernel_source_hash(),
+        "tuning_overrides": {str(k): v for k, v in tuned.items()} or None,
         "pct_hbm_peak_step": round(100.0 * value / HBM_PEAK_GBS, 2),
     }
 
@@ -234,7 +249,8 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     if not args.no_sweep:
-        out["sweep"] = bench_sweep(q, wl, dev, log, [int(v) for v in args.ns.split(",") if v])
+        out["sweep"] = bench_sweep(q, wl, dev, log, [int(v) for v in args.ns.split(",") if v],
+                                   ks=tuple(int(v) for v in args.sweep_ks.split(",") if v))
 
     if not args.no_batched:
         out["batched"] = bench_batched(q, wl, dev, log)
@@ -245,16 +261,17 @@ def main() -> int:
     return 0
 
 
-def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25):
-    """Column sweep m = 2^25, n in ns, sigma log-spaced to 10^-k, k in {0, 4, 8}:
-    accuracy of TSQR and CholQR2 for every (n, k); timing (k = 4) of the
-    TSQR launch (HIP events around it) and of the whole CholQR2 call."""
+def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8)):
+    """Column sweep m = 2^25, n in ns, sigma log-spaced to 10^-k, k in ks
+    (default {0, 4, 8}): accuracy of TSQR and CholQR2 for every (n, k); timing
+    (k = 4) of the TSQR launch (HIP events around it) and of the whole
+    CholQR2 call."""
     import numpy as np
     import torch
     sweep = []
     for ns in ns:
-        rec = {"n": ns, "m": m}
-        for k in (0, 4, 8):
+        rec = {"n": ns, "m": m, "rows_per_lane": q.qless_tune_get(ns)["rows_per_lane"]}
+        for k in ks:
             log("sweep m=2^25 n=%d k=%d" % (ns, k))
             Xs, R0s = wl.config3(ns, k, m=m, device=dev)
             Rs = torch.empty((ns, ns), dtype=torch.float64, device=dev)
