@@ -155,10 +155,11 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     p.wpb = waves_per_block_for(in->npad, in->rpl);
     // Each launch leaves one triangle per workgroup.  Tree for n <= 16:
     // fan-in levels of one panel per wavefront (fan_in = panel / n) until the
-    // remaining triangles fit one panel per wavefront of the one-workgroup
-    // last level, which then writes R.  Wider n: fan-in 16 levels throughout.
+    // remaining triangles fit two panels per wavefront of the one-workgroup
+    // last level, which then writes R (two panels there cost less than one
+    // more launch).  Wider n: fan-in 16 levels throughout.
     p.block_tree = find_tree(in->npad, in->rpl) != nullptr;
-    p.tree_rows = p.block_tree ? panel : 0;
+    p.tree_rows = p.block_tree ? 2 * panel : 0;
     p.fan_in = t.fan_in ? t.fan_in : (p.block_tree ? (int)std::max<int64_t>(2, panel / n) : 16);
     p.k1 = ceil_div(p.k0, p.wpb);
     int levels = 0;

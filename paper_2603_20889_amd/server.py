@@ -9,11 +9,12 @@ Serving loop (continuous batching, not a queue alone):
   * requests wait in an admission queue until their HBM footprint
     (8 m (n+1) bytes of data plus the (n+1)^2 running R) fits the budget and
     an active slot is free;
-  * every step folds the next chunk of rows of EVERY active request into its
-    running R, all in one batched launch (``BatchPlan`` with accumulate), so
-    work of requests that arrived at different times overlaps on the device;
-    requests with little work left get all of it and the rest of the step's
-    byte budget goes to the others oldest first, so short requests do not wait
+  * every step folds a chunk of rows of each active request the step's byte
+    budget reaches into its running R (one batched launch, ``BatchPlan`` with
+    accumulate, or the single-matrix update calls back to back on one
+    stream), so work of requests that arrived at different times overlaps on
+    the device; requests with little work left get all of it and the rest of
+    the budget goes to the others oldest first, so short requests do not wait
     behind long ones and long ones keep their arrival order;
     R([R_old; chunk]) = R([rows so far; chunk]) makes the n x n R the whole
     per-request state, and it stays on the device;
