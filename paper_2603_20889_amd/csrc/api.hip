@@ -191,9 +191,9 @@ int cholqr2_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int
     st = check_work(work, work_bytes, gw.bytes);
     if (st != QLESS_OK) return st;
     const int ni = (int)n;
-    hipError_t e = launch_gram(X, m, n, ldx, nullptr, gw.Cpart, gw.C, gp, stream);      // C = X^T X
+    hipError_t e = launch_gram(X, m, n, ldx, nullptr, false, gw.Cpart, gw.C, gp, stream); // C = X^T X
     if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, gw.A1, gw.A2, gw.iw, 0, stream);  // R1, R1^{-1}
-    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, gw.A2, gw.Cpart, gw.C, gp, stream); // (X/R1)^T (X/R1)
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, gw.A2, true, gw.Cpart, gw.C, gp, stream); // (X/R1)^T (X/R1)
     if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, gw.A3, gw.A4, gw.iw, ni, stream); // R2
     if (e == hipSuccess) e = launch_trmm_out(gw.A3, gw.A1, ni, R, ldr, gw.iw, stream);   // R = R2 R1
     if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
@@ -218,10 +218,10 @@ int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_
     double* lam1 = gw.vec;
     double* zdst = (out == QLESS_SVQB_QZ) ? Z_or_R : Zt;
     const int64_t zld = (out == QLESS_SVQB_QZ) ? ldz : n;
-    hipError_t e = launch_gram(X, m, n, ldx, nullptr, gw.Cpart, gw.C, gp, stream);
+    hipError_t e = launch_gram(X, m, n, ldx, nullptr, false, gw.Cpart, gw.C, gp, stream);
     if (e == hipSuccess)
         e = launch_svqb_eig(gw.C, ni, trunc_tol, 1, U1, lam1, D1, sigma, nullptr, 0, gw.iw, stream);
-    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, D1, gw.Cpart, gw.C, gp, stream);
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, D1, false, gw.Cpart, gw.C, gp, stream);
     if (e == hipSuccess)
         e = launch_svqb_eig(gw.C, ni, trunc_tol, 0, U1, lam1, nullptr, nullptr, zdst, zld, gw.iw, stream);
     if (e == hipSuccess && out == QLESS_SVQB_R) {

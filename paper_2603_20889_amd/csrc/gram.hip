@@ -105,7 +105,11 @@ constexpr int gram_accs() {
     return NB == 1 ? 4 : NB * (NB + 1) / 2;
 }
 
-template <int NB, bool HAS_M>
+// MK: 0 pass 1 (no M); 1 pass 2 with a dense M; 2 pass 2 with an upper
+// triangular M (CholQR2's R1^{-1}), whose blocks below the diagonal are zero
+// and are skipped: block (k, J) of M, rows 4k.., columns 16J.., is zero when
+// 4k > 16J + 15.
+template <int NB, int MK>
 __device__ __forceinline__ void gram_stage(const GramStage<NB>& b, const double* __restrict__ Ms,
                                            f64x4 (&acc)[gram_accs<NB>()], int lo, int hi) {
     constexpr int NPAD = 16 * NB;
@@ -113,7 +117,7 @@ __device__ __forceinline__ void gram_stage(const GramStage<NB>& b, const double*
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         f64x4 y[NB];
-        if constexpr (HAS_M) {
+        if constexpr (MK != 0) {
             // M stays in LDS: its operands are re-read for every block rather
             // than held in NB * 4NB registers
             asm volatile("" ::: "memory");
@@ -123,8 +127,9 @@ __device__ __forceinline__ void gram_stage(const GramStage<NB>& b, const double*
             for (int k = 0; k < 4 * NB; ++k)
 #pragma unroll
                 for (int J = 0; J < NB; ++J)
-                    y[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(b.v[u][k], Ms[(4 * k + hi) * NPAD + 16 * J + lo], y[J],
-                                                               0, 0, 0);
+                    if (MK == 1 || k < 4 * (J + 1))
+                        y[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(b.v[u][k], Ms[(4 * k + hi) * NPAD + 16 * J + lo],
+                                                                   y[J], 0, 0, 0);
         } else {
 #pragma unroll
             for (int J = 0; J < NB; ++J)
@@ -151,7 +156,7 @@ __device__ __forceinline__ void gram_stage(const GramStage<NB>& b, const double*
 // double-buffered: the loads of stage s+1 are issued before stage s is
 // multiplied (the last full stage is requested twice, so every iteration
 // issues the same loads).  The partial stage at the end loads guarded.
-template <int NB, bool HAS_M, bool GUARD>
+template <int NB, int MK, bool GUARD>
 __device__ __forceinline__ void gram_range(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
                                            int64_t r_end, const double* __restrict__ Ms,
                                            f64x4 (&acc)[gram_accs<NB>()], int lo, int hi) {
@@ -160,14 +165,14 @@ __device__ __forceinline__ void gram_range(const double* __restrict__ X, int n, 
     if (nfull > 0) {
         const int64_t last = r_begin + (nfull - 1) * STAGE;   // start of the last full stage
         GramStage<NB> ba, bb;
-        gram_load_stage<NB, HAS_M, GUARD>(ba, X, n, ldx, r_begin, r_end, lo, hi);
+        gram_load_stage<NB, MK != 0, GUARD>(ba, X, n, ldx, r_begin, r_end, lo, hi);
         for (int64_t r0 = r_begin;;) {
-            gram_load_stage<NB, HAS_M, GUARD>(bb, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
-            gram_stage<NB, HAS_M>(ba, Ms, acc, lo, hi);
+            gram_load_stage<NB, MK != 0, GUARD>(bb, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
+            gram_stage<NB, MK>(ba, Ms, acc, lo, hi);
             r0 += STAGE;
             if (r0 > last) break;
-            gram_load_stage<NB, HAS_M, GUARD>(ba, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
-            gram_stage<NB, HAS_M>(bb, Ms, acc, lo, hi);
+            gram_load_stage<NB, MK != 0, GUARD>(ba, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
+            gram_stage<NB, MK>(bb, Ms, acc, lo, hi);
             r0 += STAGE;
             if (r0 > last) break;
         }
@@ -175,20 +180,20 @@ __device__ __forceinline__ void gram_range(const double* __restrict__ X, int n, 
     const int64_t rt = r_begin + nfull * STAGE;
     if (rt < r_end) {
         GramStage<NB> bt;
-        gram_load_stage<NB, HAS_M, true>(bt, X, n, ldx, rt, r_end, lo, hi);
-        gram_stage<NB, HAS_M>(bt, Ms, acc, lo, hi);
+        gram_load_stage<NB, MK != 0, true>(bt, X, n, ldx, rt, r_end, lo, hi);
+        gram_stage<NB, MK>(bt, Ms, acc, lo, hi);
     }
 }
 
 // One wavefront per contiguous row range (gram_range).
-template <int NB, bool HAS_M>
+template <int NB, int MK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gram_mfma_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
                  int64_t nwaves, const double* __restrict__ M, double* __restrict__ Cpart) {
     constexpr int NPAD = 16 * NB;
     constexpr int NA = gram_accs<NB>();
-    __shared__ double Ms[HAS_M ? NPAD * NPAD : 1];
-    if constexpr (HAS_M) {
+    __shared__ double Ms[MK != 0 ? NPAD * NPAD : 1];
+    if constexpr (MK != 0) {
         for (int e = threadIdx.x; e < NPAD * NPAD; e += blockDim.x) {
             const int k = e / NPAD, c = e % NPAD;
             Ms[e] = (k < n && c < n) ? M[(int64_t)k * n + c] : 0.0;
@@ -205,8 +210,8 @@ gram_mfma_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     for (int t = 0; t < NA; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
-    if (n == NPAD) gram_range<NB, HAS_M, false>(X, n, ldx, r_begin, r_end, Ms, acc, lo, hi);
-    else gram_range<NB, HAS_M, true>(X, n, ldx, r_begin, r_end, Ms, acc, lo, hi);
+    if (n == NPAD) gram_range<NB, MK, false>(X, n, ldx, r_begin, r_end, Ms, acc, lo, hi);
+    else gram_range<NB, MK, true>(X, n, ldx, r_begin, r_end, Ms, acc, lo, hi);
     if constexpr (NB == 1) acc[0] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     // tile (I, J): this lane holds C[16I + 4v + hi][16J + lo]; the lower tiles
     // are the transposes of the upper ones
@@ -350,10 +355,10 @@ hipError_t launch_gram_rows(const double* X, int64_t m, int n, int64_t ldx, int6
     return hipGetLastError();
 }
 
-template <int NB, bool HAS_M>
+template <int NB, int MK>
 hipError_t launch_gram_mfma(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
                             const double* M, double* Cpart, hipStream_t s) {
-    hipLaunchKernelGGL((gram_mfma_kernel<NB, HAS_M>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n, ldx,
+    hipLaunchKernelGGL((gram_mfma_kernel<NB, MK>), dim3((unsigned)ceil_div(nw, 4)), dim3(256), 0, s, X, m, n, ldx,
                        rpw, nw, M, Cpart);
     return hipGetLastError();
 }
@@ -382,8 +387,8 @@ GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus) {
     return p;
 }
 
-hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, double* Cpart,
-                       double* C, const GramPlan& plan, hipStream_t s) {
+hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, bool m_upper,
+                       double* Cpart, double* C, const GramPlan& plan, hipStream_t s) {
     const int ni = (int)n;
     hipError_t e = hipErrorInvalidValue;
     timing_begin(kTimeGram, s);
@@ -397,8 +402,9 @@ hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const
         break;
 #define QLESS_GMFMA(NB)                                                                           \
     case 16 * NB:                                                                                 \
-        e = hm ? launch_gram_mfma<NB, true>(X, m, ni, ldx, rpw, k, M, Cpart, s)                   \
-               : launch_gram_mfma<NB, false>(X, m, ni, ldx, rpw, k, M, Cpart, s);                 \
+        e = !hm       ? launch_gram_mfma<NB, 0>(X, m, ni, ldx, rpw, k, M, Cpart, s)             \
+            : m_upper ? launch_gram_mfma<NB, 2>(X, m, ni, ldx, rpw, k, M, Cpart, s)             \
+                      : launch_gram_mfma<NB, 1>(X, m, ni, ldx, rpw, k, M, Cpart, s);            \
         break;
         QLESS_GROWS(1) QLESS_GROWS(2) QLESS_GROWS(4) QLESS_GROWS(8)
         QLESS_GMFMA(1) QLESS_GMFMA(2) QLESS_GMFMA(3) QLESS_GMFMA(4)

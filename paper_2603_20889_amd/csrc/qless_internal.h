@@ -240,9 +240,11 @@ struct GramPlan {
 GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus);
 
 // C = (X M)^T (X M) (M == nullptr: C = X^T X), via k wavefront partials in
-// Cpart and a fixed-order sum into C (n x n, ld n).
-hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, double* Cpart,
-                       double* C, const GramPlan& plan, hipStream_t stream);
+// Cpart and a fixed-order sum into C (n x n, ld n).  m_upper: M is upper
+// triangular with exact zeros below the diagonal, which the matrix-core
+// kernel then does not multiply.
+hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, bool m_upper,
+                       double* Cpart, double* C, const GramPlan& plan, hipStream_t stream);
 
 // Small n x n device steps (small.hip); every kernel runs as one workgroup.
 // Upper Cholesky C = R^T R with R^{-1}; sets *info = info_base + j on a
