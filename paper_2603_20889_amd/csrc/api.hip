@@ -252,7 +252,7 @@ int qless_batch_plan_create(const qless_matrix_desc* descs, int32_t count, int64
     return batch_plan_create(descs, count, tile_bytes, waves_per_cu, plan);
 }
 
-void qless_batch_plan_destroy(qless_batch_plan* plan) { delete plan; }
+void qless_batch_plan_destroy(qless_batch_plan* plan) { batch_plan_destroy(plan); }
 
 size_t qless_batch_plan_workspace_bytes(const qless_batch_plan* plan) { return batch_plan_bytes(plan); }
 

@@ -191,6 +191,7 @@ int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStrea
     return QLESS_OK;
 }
 
+void batch_plan_destroy(qless_batch_plan* p) { delete p; }
 size_t batch_plan_bytes(const qless_batch_plan* p) { return p ? p->bytes : 0; }
 int64_t batch_plan_tiles(const qless_batch_plan* p) { return p ? (int64_t)p->tiles.size() : 0; }
 

@@ -289,6 +289,7 @@ int batch_plan_upload(const qless_batch_plan* p, void* work, size_t work_bytes, 
 int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStream_t s);
 size_t batch_plan_bytes(const qless_batch_plan* p);
 int64_t batch_plan_tiles(const qless_batch_plan* p);
+void batch_plan_destroy(qless_batch_plan* p);   // where the plan type is complete
 
 // Benchmark timing hooks (api.hip).
 void timing_begin(int which, hipStream_t stream);

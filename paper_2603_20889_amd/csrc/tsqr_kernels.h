@@ -890,6 +890,13 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
     }
 }
 
+// The n = 64 matrix-core instance needs more than 256 registers per lane
+// (one wavefront per SIMD); every other instance is built for two.
+template <int NP, int RPL>
+constexpr int fold_waves_per_eu() {
+    return (mf_instance<NP, RPL>() && NP > 48) ? 1 : 2;
+}
+
 // One launch of Alg. 2 (stage 1 or a tree level): wavefront w folds rows
 // [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle; the
 // last wavefront of each workgroup to finish folds the triangles of
@@ -899,7 +906,8 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
 // Y + blockIdx.x*ystride (leading dimension ldy).  With normalise (a single
 // workgroup, the final R), rows of a negative diagonal are negated.
 template <int NP, int RPL>
-__global__ void __launch_bounds__((64 * waves_per_block<NP, RPL>())) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__((64 * waves_per_block<NP, RPL>()))
+__attribute__((amdgpu_waves_per_eu(fold_waves_per_eu<NP, RPL>())))
 tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
                  int64_t nwaves, double* __restrict__ Y, int64_t ldy, int64_t ystride, int normalise) {
     constexpr int WPB = waves_per_block<NP, RPL>();
