@@ -1,0 +1,62 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the kernel-source
+hash that ties committed counter data to the sources it was taken on, and
+the lookup of that data."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def _fake_tree(tmp_path, body):
+    csrc = tmp_path / "paper_2603_20889_amd" / "csrc"
+    csrc.mkdir(parents=True, exist_ok=True)
+    (csrc / "k.hip").write_text(body)
+    (tmp_path / "profiles").mkdir(exist_ok=True)
+    return tmp_path
+
+
+def test_source_hash_ignores_comments_and_spacing(tmp_path, monkeypatch):
+    root = _fake_tree(tmp_path, "int f(int a) { return a + 1; }  // one\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    h0 = bench.kernel_source_hash()
+    (root / "paper_2603_20889_amd" / "csrc" / "k.hip").write_text(
+        "/* reworded */\nint f(int a)   {\n  return a + 1;  // two\n}\n")
+    assert bench.kernel_source_hash() == h0
+    (root / "paper_2603_20889_amd" / "csrc" / "k.hip").write_text("int f(int a) { return a + 2; }\n")
+    assert bench.kernel_source_hash() != h0
+
+
+def test_traffic_is_used_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
+    root = _fake_tree(tmp_path, "int g() { return 0; }\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    rec = {"workload": "w", "kernel_hash": bench.kernel_source_hash(), "traffic_bytes_per_launch": 1234}
+    (root / "profiles" / "tsqr_stage1_traffic.json").write_text(json.dumps(rec))
+    assert bench.load_traffic("w") == 1234
+    assert bench.load_traffic("other workload") is None
+    (root / "paper_2603_20889_amd" / "csrc" / "k.hip").write_text("int g() { return 1; }\n")
+    assert bench.load_traffic("w") is None
+
+
+def test_committed_traffic_record_is_consistent():
+    """The committed record scales its counters as it says: FETCH_SIZE and
+    WRITE_SIZE (KiB) times the copy-kernel factors give the bytes."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "tsqr_stage1_traffic.json")))
+    c = d["calibration"]
+    rd = d["fetch_size_kib_per_dispatch"] * 1024 * c["fetch_factor"]
+    wr = d["write_size_kib_per_dispatch"] * 1024 * c["write_factor"]
+    assert abs(rd - d["read_bytes_per_launch"]) <= 1e-5 * rd
+    assert abs(rd + wr - d["traffic_bytes_per_launch"]) <= 1e-5 * (rd + wr)
+    assert abs(c["fetch_factor"] - 1048576 / c["fetch_size_kib"]) < 1e-5
+    assert d["traffic_bytes_per_launch"] >= d["algorithmic_bytes_per_launch"]
