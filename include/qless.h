@@ -155,7 +155,7 @@ int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
  * autotuner: waves_per_cu = stage-1 wavefronts per compute unit (row blocks
  * k = CUs * waves_per_cu; 0 = default 8, at most 32), fan_in = blocks combined
  * per tree wavefront (0 = default: one panel of stacked rows for n <= 16,
- * else 16; explicit values 2..256), rows_per_lane = panel rows
+ * else 4; explicit values 2..256), rows_per_lane = panel rows
  * per lane, one of the compiled variants for that n (0 = default;
  * QLESS_ERR_UNSUPPORTED if no such variant).  For n padding to 32, 48 or 64
  * columns, rows_per_lane = 1 selects the blocked fold on the FP64 matrix

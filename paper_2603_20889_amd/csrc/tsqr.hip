@@ -157,10 +157,12 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
     // fan-in levels of one panel per wavefront (fan_in = panel / n) until the
     // remaining triangles fit two panels per wavefront of the one-workgroup
     // last level, which then writes R (two panels there cost less than one
-    // more launch).  Wider n: fan-in 16 levels throughout.
+    // more launch).  Wider n: fan-in 4 levels throughout -- a wavefront's
+    // fold of 4n stacked rows is short, and the level keeps enough
+    // wavefronts busy (at n = 64, fan-in 16 took 1.4 ms of tree, 4 took 0.8).
     p.block_tree = find_tree(in->npad, in->rpl) != nullptr;
     p.tree_rows = p.block_tree ? 2 * panel : 0;
-    p.fan_in = t.fan_in ? t.fan_in : (p.block_tree ? (int)std::max<int64_t>(2, panel / n) : 16);
+    p.fan_in = t.fan_in ? t.fan_in : (p.block_tree ? (int)std::max<int64_t>(2, panel / n) : 4);
     p.k1 = ceil_div(p.k0, p.wpb);
     int levels = 0;
     int64_t k = p.k1;

@@ -16,11 +16,11 @@ def reset_tuning():
 
 def test_defaults_and_round_trip():
     # default fan-in for n <= 16: one panel (64 lanes x rows_per_lane rows) of
-    # stacked n-row triangles per tree wavefront; 16 for wider n
+    # stacked n-row triangles per tree wavefront; 4 for wider n
     d = q.qless_tune_get(8)
     assert d == {"waves_per_cu": 8, "fan_in": 64 * 4 // 8, "rows_per_lane": 4}
     assert q.qless_tune_get(16)["fan_in"] == 64 * 4 // 16
-    assert q.qless_tune_get(32)["fan_in"] == 16
+    assert q.qless_tune_get(32)["fan_in"] == 4
     q.qless_tune_set(8, 12, 32, 4)
     assert q.qless_tune_get(8) == {"waves_per_cu": 12, "fan_in": 32, "rows_per_lane": 4}
 
