@@ -22,7 +22,7 @@ import time
 import paper_2603_20889_amd as q
 
 WAVES_PER_CU = (4, 8, 12, 16)
-FAN_IN = (0, 8, 16, 32)   # 0: the library default
+FAN_IN = (0, 4, 8, 16, 32)   # 0: the library default
 
 
 def cache_path() -> str:
