@@ -22,20 +22,27 @@ def test_more_than_one_gpu_is_refused():
 def _fake_tree(tmp_path, body):
     csrc = tmp_path / "paper_2603_20889_amd" / "csrc"
     csrc.mkdir(parents=True, exist_ok=True)
-    (csrc / "k.hip").write_text(body)
+    (csrc / "tsqr_k.hip").write_text(body)
+    (csrc / "api.hip").write_text("int entry() { return 0; }\n")
     (tmp_path / "profiles").mkdir(exist_ok=True)
     return tmp_path
 
 
 def test_source_hash_ignores_comments_and_spacing(tmp_path, monkeypatch):
     root = _fake_tree(tmp_path, "int f(int a) { return a + 1; }  // one\n")
+    csrc = root / "paper_2603_20889_amd" / "csrc"
     monkeypatch.setattr(bench, "ROOT", str(root))
     h0 = bench.kernel_source_hash()
-    (root / "paper_2603_20889_amd" / "csrc" / "k.hip").write_text(
-        "/* reworded */\nint f(int a)   {\n  return a + 1;  // two\n}\n")
+    (csrc / "tsqr_k.hip").write_text("/* reworded */\nint f(int a)   {\n  return a + 1;  // two\n}\n")
     assert bench.kernel_source_hash() == h0
-    (root / "paper_2603_20889_amd" / "csrc" / "k.hip").write_text("int f(int a) { return a + 2; }\n")
+    # entry-point glue is not a profiled source
+    (csrc / "api.hip").write_text("int entry() { return 1; }\n")
+    assert bench.kernel_source_hash() == h0
+    (csrc / "tsqr_k.hip").write_text("int f(int a) { return a + 2; }\n")
     assert bench.kernel_source_hash() != h0
+    h1 = bench.kernel_source_hash()
+    (csrc / "gram.hip").write_text("int g() { return 0; }\n")
+    assert bench.kernel_source_hash() != h1
 
 
 def test_traffic_is_used_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
@@ -45,7 +52,7 @@ def test_traffic_is_used_only_for_the_sources_it_was_taken_on(tmp_path, monkeypa
     (root / "profiles" / "tsqr_stage1_traffic.json").write_text(json.dumps(rec))
     assert bench.load_traffic("w") == 1234
     assert bench.load_traffic("other workload") is None
-    (root / "paper_2603_20889_amd" / "csrc" / "k.hip").write_text("int g() { return 1; }\n")
+    (root / "paper_2603_20889_amd" / "csrc" / "tsqr_k.hip").write_text("int g() { return 1; }\n")
     assert bench.load_traffic("w") is None
 
 
