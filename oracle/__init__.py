@@ -12,6 +12,8 @@ Paper: Thies & Roehrig-Zoellner, arXiv 2603.20889.
   householder_r : R of X, Sec. 1 (X = QR, R upper triangular), per-column
                   Householder reflector of Alg. 4 without the column pairing
   cholqr2_r     : Q-less Cholesky-QR2, Alg. 1
+  shifted_cholqr3_r : Q-less shifted Cholesky-QR3, the robust variant Sec. 2
+                  names (shift of Fukaya et al. 2020)
   svqb2         : Q-less SVQB applied twice; QZ form of Sec. 1, SVQB2
                   paragraph of Sec. 3.1
   lstsq_from_r  : least squares via the Q-less R of [A b], Sec. 1
@@ -55,6 +57,8 @@ def _load():
         lib.oracle_householder_r.restype = ctypes.c_int
         lib.oracle_cholqr2_r.argtypes = [dp, i64, i64, i64, dp]
         lib.oracle_cholqr2_r.restype = ctypes.c_int
+        lib.oracle_shifted_cholqr3_r.argtypes = [dp, i64, i64, i64, dp]
+        lib.oracle_shifted_cholqr3_r.restype = ctypes.c_int
         lib.oracle_svqb2.argtypes = [dp, i64, i64, i64, ctypes.c_double, dp, dp, dp]
         lib.oracle_svqb2.restype = ctypes.c_int
         lib.oracle_jacobi_eig.argtypes = [dp, i64, dp, dp]
@@ -105,6 +109,17 @@ def cholqr2_r(X) -> tuple[np.ndarray, int]:
     rc = _load().oracle_cholqr2_r(_ptr(X), m, n, ldx, _ptr(R))
     if rc < 0:
         raise RuntimeError("oracle_cholqr2_r failed: %d" % rc)
+    return R, rc
+
+
+def shifted_cholqr3_r(X) -> tuple[np.ndarray, int]:
+    """Q-less shifted CholQR3.  Returns (R, info); info = j, n+j or 2n+j on a
+    non-positive pivot in the shifted or one of the two later Choleskys."""
+    X, m, n, ldx = _as_rowmajor(X)
+    R = np.empty((n, n), dtype=np.float64)
+    rc = _load().oracle_shifted_cholqr3_r(_ptr(X), m, n, ldx, _ptr(R))
+    if rc < 0:
+        raise RuntimeError("oracle_shifted_cholqr3_r failed: %d" % rc)
     return R, rc
 
 

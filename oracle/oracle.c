@@ -13,6 +13,7 @@
  * Contents (each function names the passage it follows):
  *   oracle_householder_r  R of X by unblocked Householder QR       (Sec. 1 problem statement; Alg. 4 per-column reflector)
  *   oracle_cholqr2_r      Q-less Cholesky-QR2                      (Sec. 3.1, Alg. 1)
+ *   oracle_shifted_cholqr3_r  Q-less shifted Cholesky-QR3          (Sec. 2 related work; shift of Fukaya et al. 2020)
  *   oracle_svqb2          Q-less SVQB applied twice, QZ form         (Sec. 1 SVQB/QZ definition; Sec. 3.1 SVQB2 paragraph)
  *   oracle_jacobi_eig     symmetric eigendecomposition (cyclic Jacobi, Golub & Van Loan Sec. 8.5) used by SVQB2
  *   oracle_lstsq_from_r   least squares from the Q-less R of [A b]   (Sec. 1, single-pass least squares)
@@ -209,6 +210,63 @@ breakdown:
     for (int64_t i = 0; i < n * n; ++i) R[i] = NAN;
 done:
     free(C); free(R1); free(R2); free(Y);
+    return rc;
+}
+
+/* Q-less shifted Cholesky-QR3 -- the robust Gram variant for ill-conditioned
+ * X that Sec. 2 names; the shift is the one of Fukaya, Kannan, Nakatsukasa,
+ * Zhang and Yamamoto (SIAM J. Sci. Comput. 42, 2020):
+ *   C = X^T X;  s = 11 (m n + n (n + 1)) u ||X||^2 with u = 2^-53 and
+ *   ||X||^2 taken as ||X||_F^2 = trace C (an upper bound of ||X||_2^2, so the
+ *   shift is never smaller than the published one);
+ *   R1 = chol(C + s I);  Y = X R1^{-1} (forward substitution, row by row);
+ *   R23 = Q-less CholQR2 of Y;  R = R23 R1.
+ * Returns 0; j (1..n) if chol(C + s I) breaks down at column j, n + j or
+ * 2n + j for the two CholQR2 passes; -1 bad args, -2 no memory.  On
+ * breakdown R is filled with NaN. */
+int oracle_shifted_cholqr3_r(const double *X, int64_t m, int64_t n, int64_t ldx, double *R)
+{
+    if (n < 1 || m < 0 || (m > 0 && (X == NULL || ldx < n)) || R == NULL)
+        return -1;
+    double *C = (double *)malloc((size_t)(n * n) * sizeof(double));
+    double *R1 = (double *)malloc((size_t)(n * n) * sizeof(double));
+    double *R23 = (double *)malloc((size_t)(n * n) * sizeof(double));
+    double *Y = (double *)malloc((size_t)((m > 0 ? m : 1) * n) * sizeof(double));
+    int rc = 0;
+    if (!C || !R1 || !R23 || !Y) { rc = -2; goto done; }
+
+    gram(X, m, n, ldx, C);
+    double tr = 0.0;
+    for (int64_t j = 0; j < n; ++j) tr = tr + C[j * n + j];
+    const double shift = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-53 * tr;
+    for (int64_t j = 0; j < n; ++j) C[j * n + j] = C[j * n + j] + shift;
+    rc = cholesky_upper(C, n, R1);
+    if (rc != 0) goto breakdown;
+
+    for (int64_t i = 0; i < m; ++i) {
+        const double *x = X + i * ldx;
+        double *y = Y + i * n;
+        for (int64_t c = 0; c < n; ++c) {
+            double e = x[c];
+            for (int64_t k = 0; k < c; ++k) e = e - y[k] * R1[k * n + c];
+            y[c] = e / R1[c * n + c];
+        }
+    }
+    rc = oracle_cholqr2_r(Y, m, n, n, R23);
+    if (rc < 0) goto done;
+    if (rc > 0) { rc += (int)n; goto breakdown; }
+
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < n; ++c) {
+            double acc = 0.0;
+            for (int64_t k = i; k <= c; ++k) acc = acc + R23[i * n + k] * R1[k * n + c];
+            R[i * n + c] = (c >= i) ? acc : 0.0;
+        }
+    goto done;
+breakdown:
+    for (int64_t i = 0; i < n * n; ++i) R[i] = NAN;
+done:
+    free(C); free(R1); free(R23); free(Y);
     return rc;
 }
 

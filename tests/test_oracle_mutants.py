@@ -90,3 +90,68 @@ def test_battery_rejects_mutant(tmp_path, name):
     lib = build_mutant(tmp_path, name)
     with np.errstate(all="ignore"):
         assert not pins_pass(lambda X: mutant_r(lib, X)), name
+
+
+# Shifted CholQR3: mistakes planted inside oracle_shifted_cholqr3_r only.
+MUTANTS_SHIFTED = {
+    "no_shift": ("C[j * n + j] = C[j * n + j] + shift;", "C[j * n + j] = C[j * n + j];"),
+    "negative_shift": ("C[j * n + j] = C[j * n + j] + shift;", "C[j * n + j] = C[j * n + j] - shift;"),
+    "first_factor_dropped": ("acc = acc + R23[i * n + k] * R1[k * n + c];",
+                             "acc = acc + R23[i * n + k] * (k == c ? 1.0 : 0.0);"),
+    "factors_reversed": ("acc = acc + R23[i * n + k] * R1[k * n + c];",
+                         "acc = acc + R1[i * n + k] * R23[k * n + c];"),
+    "substitution_sign": ("for (int64_t k = 0; k < c; ++k) e = e - y[k] * R1[k * n + c];",
+                          "for (int64_t k = 0; k < c; ++k) e = e + y[k] * R1[k * n + c];"),
+}
+
+
+def build_shifted_mutant(tmp_path, name):
+    old, new = MUTANTS_SHIFTED[name]
+    src = open(SRC).read()
+    start = src.index("int oracle_shifted_cholqr3_r(")
+    body = src[start:]
+    assert body.count(old) >= 1, name
+    src = src[:start] + body.replace(old, new, 1)
+    c = tmp_path / ("%s.c" % name)
+    so = tmp_path / ("%s.so" % name)
+    c.write_text(src)
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-w", str(c), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_shifted_cholqr3_r.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp]
+    lib.oracle_shifted_cholqr3_r.restype = ctypes.c_int
+    return lib
+
+
+def shifted_mutant_r(lib, X):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    R = np.empty((n, n))
+    dp = ctypes.POINTER(ctypes.c_double)
+    info = lib.oracle_shifted_cholqr3_r(X.ctypes.data_as(dp), m, n, n, R.ctypes.data_as(dp))
+    return R, info
+
+
+def shifted_pins_pass(r_of) -> bool:
+    # well conditioned: the known R0
+    Xk, R0 = wl.known_r(2000, 6, wl.logspace_sigma(6, 3), seed=1)
+    R, info = r_of(Xk)
+    if info != 0 or not np.all(np.isfinite(R)) or oracle.rel_err_r(R, R0) > 1e-12:
+        return False
+    # kappa = 1e12 spread over the columns: completes, backward stable
+    Xs = wl.svd_form(2000, 8, wl.logspace_sigma(8, 12), seed=9)
+    R, info = r_of(Xs)
+    if info != 0 or not np.all(np.isfinite(R)) or oracle.gram_residual(Xs, R) > 1e-14:
+        return False
+    return oracle.rel_err_r(R, oracle.householder_r(Xs)) <= 1e-12
+
+
+def test_shifted_battery_accepts_real_oracle():
+    assert shifted_pins_pass(oracle.shifted_cholqr3_r)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_SHIFTED))
+def test_shifted_battery_rejects_mutant(tmp_path, name):
+    lib = build_shifted_mutant(tmp_path, name)
+    with np.errstate(all="ignore"):
+        assert not shifted_pins_pass(lambda X: shifted_mutant_r(lib, X)), name

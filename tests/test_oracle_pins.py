@@ -234,6 +234,58 @@ def test_cholqr2_breakdown_reports_column():
     assert np.isnan(R).all()
 
 
+# ------------------------------------------ shifted CholQR3 (robust variant)
+
+@pytest.mark.parametrize("n,k", [(4, 0), (8, 4), (16, 4), (32, 2)])
+def test_shifted_cholqr3_postcondition_and_agreement(n, k):
+    """Well-conditioned X: (X R^{-1})^T (X R^{-1}) = I and R equals the
+    known R0 (and so the Householder R) to the CholQR2 bar."""
+    X, R0 = wl.known_r(5000, n, wl.logspace_sigma(n, k), seed=79 + n)
+    R, info = oracle.shifted_cholqr3_r(X)
+    assert info == 0
+    Q = sla.solve_triangular(R, X.T, trans="T", lower=False).T
+    assert np.linalg.norm(oracle.gram_dot2(Q) - np.eye(n)) <= 1e-13
+    assert oracle.rel_err_r(R, R0) <= 1e-12
+    assert oracle.rel_err_r(R, oracle.householder_r(X)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,k", [(8, 10), (16, 12), (5, 12)])
+def test_shifted_cholqr3_beyond_cholqr2(n, k):
+    """kappa = 10^k far above eps^{-1/2}, spread over all columns
+    (X = U diag(sigma) V^T): CholQR2's Gram matrix is numerically singular
+    and a Cholesky fails; the shifted variant completes, its R is backward
+    stable (Gram residual against the extended-precision X^T X at the level
+    of u) and agrees with the Householder R normwise."""
+    X = wl.svd_form(4000, n, wl.logspace_sigma(n, k), seed=83 + n + k)
+    _, info2 = oracle.cholqr2_r(X)
+    assert info2 != 0
+    R, info = oracle.shifted_cholqr3_r(X)
+    assert info == 0
+    assert np.all(np.diag(R) > 0.0) and np.all(np.tril(R, -1) == 0.0)
+    assert oracle.gram_residual(X, R) <= 1e-14
+    assert oracle.rel_err_r(R, oracle.householder_r(X)) <= 1e-12
+
+
+def test_shifted_cholqr3_scaled_orthogonal_columns():
+    """Orthogonal columns of lengths 2^a: R = diag(2^a) up to rounding,
+    whatever the (tiny) shift did to the first factor."""
+    n = 6
+    Q = wl.orthonormal_columns(3000, n, wl.rng(5))
+    d = 2.0 ** np.array([0, 3, -2, 7, 1, -5])
+    R, info = oracle.shifted_cholqr3_r(Q * d)
+    assert info == 0
+    assert oracle.rel_err_r(R, np.diag(d)) <= 1e-14
+
+
+def test_shifted_cholqr3_zero_column_still_breaks_down():
+    """An exactly zero column stays singular after the shift only if the
+    shift is zero; with X = 0 the trace, and so the shift, is zero and the
+    first Cholesky reports column 1."""
+    R, info = oracle.shifted_cholqr3_r(np.zeros((100, 3)))
+    assert info == 1
+    assert np.isnan(R).all()
+
+
 # --------------------------------------------------------------- SVQB2
 
 def test_jacobi_matches_lapack_eigh():

@@ -116,6 +116,16 @@ def known_r(m: int, n: int, sigma, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return Q0 @ R0, R0
 
 
+def svd_form(m: int, n: int, sigma, seed: int) -> np.ndarray:
+    """X = U diag(sigma) V^T with U (m x n) and V (n x n) orthonormal, each a
+    product of dense random reflectors: singular values sigma, and the
+    ill-conditioning spread over all columns rather than graded along them."""
+    g = rng(seed)
+    U = orthonormal_columns(m, n, g)
+    V = orthonormal_columns(n, n, g)
+    return (U * np.asarray(sigma, dtype=np.float64)) @ V.T
+
+
 # ------------------------------------------------- device-side construction
 
 
