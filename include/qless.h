@@ -56,7 +56,8 @@ typedef enum {
     QLESS_METHOD_TSQR = 0,       /* qless_tsqr_r */
     QLESS_METHOD_CHOLQR2 = 1,    /* cholqr2_r */
     QLESS_METHOD_SVQB = 2,       /* svqb */
-    QLESS_METHOD_TSQR_UPDATE = 3 /* qless_tsqr_r_update */
+    QLESS_METHOD_TSQR_UPDATE = 3, /* qless_tsqr_r_update */
+    QLESS_METHOD_SHIFTED_CHOLQR3 = 4 /* shifted_cholqr3_r */
 } qless_method;
 
 typedef enum {
@@ -119,6 +120,27 @@ int qless_tsqr_r_update(const double *X, int64_t m, int64_t n, int64_t ldx,
 int cholqr2_r(const double *X, int64_t m, int64_t n, int64_t ldx,
               double *R, int64_t ldr, int32_t *info, void *work,
               size_t work_bytes, hipStream_t stream);
+
+/*
+ * shifted_cholqr3_r -- Q-less shifted Cholesky-QR3, the robust Gram variant
+ * for ill-conditioned X that the related work (Sec. 2) names; the shift is
+ * that of Fukaya et al. (SIAM J. Sci. Comput. 42, 2020):
+ * C = X^T X; s = 11 (m n + n (n + 1)) u trace(C) with u = 2^-53 (trace C =
+ * ||X||_F^2 bounds ||X||_2^2); R1 = chol(C + s I); then Cholesky-QR twice on
+ * X R1^{-1}: R2 = chol((X R1^{-1})^T (X R1^{-1})), R3 = chol of the Gram
+ * matrix of X R1^{-1} R2^{-1}; R = R3 R2 R1.  Three passes over X (the
+ * triangular multiplies fused into the Gram passes); the n x n steps run on
+ * the device.  Completes for kappa(X) up to about u^{-1} where CholQR2 breaks
+ * down above about u^{-1/2}.
+ *
+ * Arguments, layout, workspace (QLESS_METHOD_SHIFTED_CHOLQR3) and errors as
+ * for cholqr2_r.  info: 0; j (1..n) if the shifted Cholesky meets a
+ * non-positive pivot in column j, n + j or 2n + j for the second or third.
+ * On breakdown every entry of R is NaN.
+ */
+int shifted_cholqr3_r(const double *X, int64_t m, int64_t n, int64_t ldx,
+                      double *R, int64_t ldr, int32_t *info, void *work,
+                      size_t work_bytes, hipStream_t stream);
 
 /*
  * svqb -- Q-less SVQB applied twice (Sec. 1 and Sec. 3.1, SVQB2):

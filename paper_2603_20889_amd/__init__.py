@@ -27,6 +27,7 @@ QLESS_METHOD_TSQR = 0
 QLESS_METHOD_TSQR_UPDATE = 3
 QLESS_METHOD_CHOLQR2 = 1
 QLESS_METHOD_SVQB = 2
+QLESS_METHOD_SHIFTED_CHOLQR3 = 4
 
 QLESS_SVQB_R = 0
 QLESS_SVQB_QZ = 1
@@ -35,7 +36,7 @@ QLESS_MAX_N = 64
 
 EXPORTED = (
     "qless_status_string", "qless_version", "qless_workspace_bytes", "qless_tsqr_r", "qless_tsqr_r_update",
-    "cholqr2_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
+    "cholqr2_r", "shifted_cholqr3_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
     "qless_timing_read", "qless_batch_plan_create", "qless_batch_plan_destroy",
     "qless_batch_plan_workspace_bytes", "qless_batch_plan_tiles", "qless_batch_plan_upload",
     "qless_tsqr_r_batched", "qless_tune_set", "qless_tune_get",
@@ -80,6 +81,8 @@ def load() -> ctypes.CDLL:
     lib.qless_tsqr_r_update.restype = ctypes.c_int
     lib.cholqr2_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
     lib.cholqr2_r.restype = ctypes.c_int
+    lib.shifted_cholqr3_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
+    lib.shifted_cholqr3_r.restype = ctypes.c_int
     lib.svqb.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, i64, vp, dbl, vp, vp, sz, vp]
     lib.svqb.restype = ctypes.c_int
     lib.qless_lstsq_finish.argtypes = [vp, i64, i64, vp, vp, vp, vp]
@@ -217,6 +220,28 @@ def cholqr2_r(X, R=None, info=None, work=None):
                               ctypes.c_void_p(R.data_ptr()), R.stride(0), ctypes.c_void_p(info.data_ptr()),
                               ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
     _check(st, "cholqr2_r")
+    return R, info
+
+
+def shifted_cholqr3_r(X, R=None, info=None, work=None):
+    """Q-less shifted CholQR3.  Returns (R, info) with info a 1-element int32
+    device tensor (0 ok; j, n+j or 2n+j on Cholesky breakdown)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_SHIFTED_CHOLQR3, m, n, dev)
+        else:
+            wb = work.numel() * work.element_size()
+        st = load().shifted_cholqr3_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                                      ctypes.c_void_p(R.data_ptr()), R.stride(0), ctypes.c_void_p(info.data_ptr()),
+                                      ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
+    _check(st, "shifted_cholqr3_r")
     return R, info
 
 

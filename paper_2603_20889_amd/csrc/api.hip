@@ -76,12 +76,13 @@ static void timing_collect(TimingSlot& s) {
     s.used = 0;
 }
 
-// Workspace of the Gram-based forms: k partial Gram matrices, C, four n x n
+// Workspace of the Gram-based forms: k partial Gram matrices, C, seven n x n
 // work matrices, one n-vector and an int status word, each 256-byte aligned.
 struct GramWork {
     double* Cpart = nullptr;
     double* C = nullptr;
     double *A1 = nullptr, *A2 = nullptr, *A3 = nullptr, *A4 = nullptr;
+    double *A5 = nullptr, *A6 = nullptr, *A7 = nullptr;   // shifted CholQR3 only
     double* vec = nullptr;
     int* iw = nullptr;
     void* tsqr_work = nullptr;   // workspace of the n x n TSQR of Z (SVQB R mode)
@@ -105,12 +106,27 @@ GramWork gram_work_layout(const GramPlan& gp, int64_t n, void* base) {
     w.A2 = reinterpret_cast<double*>(take(sq));
     w.A3 = reinterpret_cast<double*>(take(sq));
     w.A4 = reinterpret_cast<double*>(take(sq));
+    w.A5 = reinterpret_cast<double*>(take(sq));
+    w.A6 = reinterpret_cast<double*>(take(sq));
+    w.A7 = reinterpret_cast<double*>(take(sq));
     w.vec = reinterpret_cast<double*>(take((size_t)n * sizeof(double)));
     w.iw = reinterpret_cast<int*>(take(sizeof(int)));
     w.tsqr_bytes = make_tsqr_plan(n, n, current_device_info().num_cus).work_bytes;
     w.tsqr_work = take(w.tsqr_bytes);
     w.bytes = off;
     return w;
+}
+
+// Shift of the shifted Cholesky-QR (Fukaya et al., SIAM J. Sci. Comput. 42,
+// 2020): C += s I with s = 11 (m n + n (n + 1)) u ||X||^2, u = 2^-53, where
+// ||X||^2 is taken as ||X||_F^2 = trace C (an upper bound of ||X||_2^2).  One
+// thread: n <= 64 additions in a fixed order.
+__global__ void __launch_bounds__(64) shift_diag_kernel(double* __restrict__ C, int n, double size_term) {
+    if (threadIdx.x != 0) return;
+    double tr = 0.0;
+    for (int j = 0; j < n; ++j) tr = tr + C[j * n + j];
+    const double shift = 11.0 * size_term * 0x1p-53 * tr;
+    for (int j = 0; j < n; ++j) C[j * n + j] = C[j * n + j] + shift;
 }
 
 }  // namespace qless
@@ -154,7 +170,8 @@ size_t qless_workspace_bytes(int method, int64_t m, int64_t n) {
         case QLESS_METHOD_TSQR: return make_tsqr_plan(m, n, d.num_cus).work_bytes;
         case QLESS_METHOD_TSQR_UPDATE: return make_tsqr_update_plan(m, n, d.num_cus).work_bytes;
         case QLESS_METHOD_CHOLQR2:
-        case QLESS_METHOD_SVQB: return gram_work_layout(make_gram_plan(m, n, d.num_cus), n, nullptr).bytes;
+        case QLESS_METHOD_SVQB:
+        case QLESS_METHOD_SHIFTED_CHOLQR3: return gram_work_layout(make_gram_plan(m, n, d.num_cus), n, nullptr).bytes;
         default: return 0;
     }
 }
@@ -228,6 +245,35 @@ int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_
         TsqrPlan tp = make_tsqr_plan(n, n, d.num_cus);
         e = launch_tsqr(Zt, n, n, n, Z_or_R, ldz, gw.tsqr_work, tp, stream);
     }
+    if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int shifted_cholqr3_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr, int32_t* info,
+                      void* work, size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, R, ldr);
+    if (st != QLESS_OK) return st;
+    const DeviceInfo& d = current_device_info();
+    GramPlan gp = make_gram_plan(m, n, d.num_cus);
+    GramWork gw = gram_work_layout(gp, n, work);
+    st = check_work(work, work_bytes, gw.bytes);
+    if (st != QLESS_OK) return st;
+    const int ni = (int)n;
+    const double size_term = (double)m * (double)n + (double)n * (double)(n + 1);
+    double *R1 = gw.A1, *R1i = gw.A2, *R2 = gw.A3, *R2i = gw.A4, *M3 = gw.A5, *R3 = gw.A6, *R3i = gw.A7;
+    hipError_t e = launch_gram(X, m, n, ldx, nullptr, false, gw.Cpart, gw.C, gp, stream);   // C = X^T X
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(shift_diag_kernel, dim3(1), dim3(64), 0, stream, gw.C, ni, size_term);   // C + s I
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, R1, R1i, gw.iw, 0, stream);
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, R1i, true, gw.Cpart, gw.C, gp, stream);  // Y = X R1^{-1}
+    if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, R2, R2i, gw.iw, ni, stream);
+    if (e == hipSuccess) e = launch_trmm_out(R1i, R2i, ni, M3, n, gw.iw, stream);             // R1^{-1} R2^{-1}
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, M3, true, gw.Cpart, gw.C, gp, stream);   // Y R2^{-1}
+    if (e == hipSuccess) e = launch_chol_inv(gw.C, ni, R3, R3i, gw.iw, 2 * ni, stream);
+    if (e == hipSuccess) e = launch_trmm_out(R2, R1, ni, M3, n, gw.iw, stream);                // R2 R1
+    if (e == hipSuccess) e = launch_trmm_out(R3, M3, ni, R, ldr, gw.iw, stream);               // R = R3 R2 R1
     if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
     return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }

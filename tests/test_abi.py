@@ -23,7 +23,8 @@ def declared_functions():
 
 def test_header_declares_expected_entry_points():
     decl = declared_functions()
-    for name in ("qless_tsqr_r", "cholqr2_r", "svqb", "qless_workspace_bytes", "qless_lstsq_finish"):
+    for name in ("qless_tsqr_r", "cholqr2_r", "shifted_cholqr3_r", "svqb", "qless_workspace_bytes",
+                 "qless_lstsq_finish"):
         assert name in decl
 
 
@@ -99,6 +100,8 @@ def test_small_problems_plan_one_wavefront():
         assert q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, n, n) == 256
     assert (q.qless_workspace_bytes(q.QLESS_METHOD_SVQB, 10_000, 64)
             >= q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2, 10_000, 64))
+    assert (q.qless_workspace_bytes(q.QLESS_METHOD_SHIFTED_CHOLQR3, 10_000, 64)
+            == q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2, 10_000, 64) > 0)
 
 
 def test_update_argument_and_workspace_errors():

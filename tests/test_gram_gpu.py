@@ -69,6 +69,46 @@ def test_cholqr2_empty_breaks_down(gpu):
 
 
 @pytest.mark.parametrize("m,n", SHAPES)
+def test_shifted_cholqr3_matches_oracle(gpu, m, n):
+    print("case shifted cholqr3 m=%d n=%d" % (m, n), flush=True)
+    X, R0 = wl.known_r(m, n, wl.logspace_sigma(n, 3), seed=m + 5 * n)
+    R, info = q.shifted_cholqr3_r(dev_tensor(X, gpu))
+    torch.cuda.synchronize(gpu)
+    assert int(info.item()) == 0
+    R = R.cpu().numpy()
+    Ro, info_o = oracle.shifted_cholqr3_r(X)
+    assert info_o == 0
+    assert oracle.rel_err_r(R, Ro) <= E_R
+    assert oracle.rel_err_r(R, oracle.householder_r(X)) <= E_R
+    assert oracle.gram_residual(X, R) <= E_G
+    assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) > 0.0)
+
+
+@pytest.mark.parametrize("m,n,k", [(20000, 8, 10), (30000, 16, 12), (12000, 48, 10), (9000, 64, 11)])
+def test_shifted_cholqr3_beyond_cholqr2(gpu, m, n, k):
+    """kappa = 10^k spread over all columns: CholQR2 breaks down on the
+    device, the shifted variant completes with a backward-stable R."""
+    print("case shifted cholqr3 kappa=1e%d m=%d n=%d" % (k, m, n), flush=True)
+    X = wl.svd_form(m, n, wl.logspace_sigma(n, k), seed=700 + n + k)
+    Xd = dev_tensor(X, gpu)
+    _, info2 = q.cholqr2_r(Xd)
+    R, info = q.shifted_cholqr3_r(Xd)
+    torch.cuda.synchronize(gpu)
+    assert int(info2.item()) != 0
+    assert int(info.item()) == 0
+    R = R.cpu().numpy()
+    assert oracle.gram_residual(X, R) <= E_G
+    assert oracle.rel_err_r(R, oracle.householder_r(X)) <= E_R
+
+
+def test_shifted_cholqr3_zero_matrix_breaks_down(gpu):
+    R, info = q.shifted_cholqr3_r(torch.zeros((500, 3), dtype=torch.float64, device=gpu))
+    torch.cuda.synchronize(gpu)
+    assert int(info.item()) == 1
+    assert torch.isnan(R).all()
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
 def test_svqb_r_mode_matches_oracle(gpu, m, n):
     print("case svqb-R m=%d n=%d" % (m, n), flush=True)
     X, R0 = wl.known_r(m, n, wl.logspace_sigma(n, 3), seed=2 * m + n)
