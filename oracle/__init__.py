@@ -17,6 +17,7 @@ Paper: Thies & Roehrig-Zoellner, arXiv 2603.20889.
   svqb2         : Q-less SVQB applied twice; QZ form of Sec. 1, SVQB2
                   paragraph of Sec. 3.1
   lstsq_from_r  : least squares via the Q-less R of [A b], Sec. 1
+  q_from_r      : explicit Q = X R^{-1} rebuilt from X and the Q-less R, Sec. 1
   gram_dot2     : X^T X in twice-working precision (error metric only)
 """
 from __future__ import annotations
@@ -65,6 +66,8 @@ def _load():
         lib.oracle_jacobi_eig.restype = ctypes.c_int
         lib.oracle_lstsq_from_r.argtypes = [dp, i64, i64, dp, dp]
         lib.oracle_lstsq_from_r.restype = ctypes.c_int
+        lib.oracle_q_from_r.argtypes = [dp, i64, i64, i64, dp, i64, dp, i64]
+        lib.oracle_q_from_r.restype = ctypes.c_int
         lib.oracle_gram_dot2.argtypes = [dp, i64, i64, i64, dp]
         lib.oracle_gram_dot2.restype = None
         _lib = lib
@@ -161,6 +164,17 @@ def lstsq_from_r(Rt) -> tuple[np.ndarray, float]:
     if rc != 0:
         raise RuntimeError("oracle_lstsq_from_r: singular R_A at %d" % rc)
     return x, float(res[0])
+
+
+def q_from_r(X, R) -> np.ndarray:
+    """Q = X R^{-1} (forward substitution per row); raises if R is singular."""
+    X, m, n, ldx = _as_rowmajor(X)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    Q = np.empty((m, n), dtype=np.float64)
+    rc = _load().oracle_q_from_r(_ptr(X), m, n, ldx, _ptr(R), n, _ptr(Q), n)
+    if rc != 0:
+        raise RuntimeError("oracle_q_from_r failed: %d" % rc)
+    return Q
 
 
 def gram_dot2(X) -> np.ndarray:

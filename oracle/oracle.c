@@ -17,6 +17,7 @@
  *   oracle_svqb2          Q-less SVQB applied twice, QZ form         (Sec. 1 SVQB/QZ definition; Sec. 3.1 SVQB2 paragraph)
  *   oracle_jacobi_eig     symmetric eigendecomposition (cyclic Jacobi, Golub & Van Loan Sec. 8.5) used by SVQB2
  *   oracle_lstsq_from_r   least squares from the Q-less R of [A b]   (Sec. 1, single-pass least squares)
+ *   oracle_q_from_r       explicit Q = X R^{-1} rebuilt from the Q-less R (Sec. 1)
  *   oracle_gram_dot2      X^T X accumulated in twice-working precision (Ogita-Rump-Oishi Dot2), for the error metric
  *
  * Conventions
@@ -416,6 +417,32 @@ int oracle_svqb2(const double *X, int64_t m, int64_t n, int64_t ldx, double trun
 done:
     free(C); free(U1); free(U2); free(l1); free(l2); free(D1); free(T); free(Y);
     return rc;
+}
+
+/* --------------------------------------------------- explicit Q from R */
+
+/* Q = X R^{-1}: Sec. 1 notes that for well-conditioned X the Q of the
+ * Q-less factorisation can be rebuilt afterwards from X and R.  Row i of Q
+ * solves q R = x_i by forward substitution (R upper triangular, row-major
+ * n x n, ldr >= n; Q row-major m x n, ldq >= n).  Returns 0; j + 1 if
+ * R_jj == 0 (Q is then not defined and left unwritten); -1 bad args. */
+int oracle_q_from_r(const double *X, int64_t m, int64_t n, int64_t ldx, const double *R, int64_t ldr,
+                    double *Q, int64_t ldq)
+{
+    if (n < 1 || m < 0 || R == NULL || ldr < n || (m > 0 && (X == NULL || Q == NULL || ldx < n || ldq < n)))
+        return -1;
+    for (int64_t j = 0; j < n; ++j)
+        if (R[j * ldr + j] == 0.0) return (int)(j + 1);
+    for (int64_t i = 0; i < m; ++i) {
+        const double *x = X + i * ldx;
+        double *q = Q + i * ldq;
+        for (int64_t c = 0; c < n; ++c) {
+            double e = x[c];
+            for (int64_t k = 0; k < c; ++k) e = e - q[k] * R[k * ldr + c];
+            q[c] = e / R[c * ldr + c];
+        }
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------ least squares */

@@ -341,3 +341,41 @@ def test_lstsq_from_r_matches_lapack(n):
     assert np.linalg.norm(x - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
     assert abs(res - np.linalg.norm(A @ x_ref - b)) <= 1e-10 * max(res, 1e-300)
     assert np.linalg.norm(x - x0) <= 1e-5 * np.linalg.norm(x0)
+
+
+# ------------------------------------------- explicit Q = X R^{-1} (Sec. 1)
+
+def test_q_from_r_identity_and_exact_scaling():
+    """R = I gives Q = X exactly; R = diag(2^a) divides column j by 2^a_j
+    exactly; an upper bidiagonal R with power-of-two entries on dyadic data
+    gives the exact rational solution of q R = x."""
+    X = wl.dyadic(50, 4, seed=3)
+    assert np.array_equal(oracle.q_from_r(X, np.eye(4)), X)
+    d = 2.0 ** np.array([3, -1, 0, 5])
+    assert np.array_equal(oracle.q_from_r(X, np.diag(d)), X / d)
+    R = np.diag(d) + np.diag([0.5, 0.25, 2.0], 1)
+    Q = oracle.q_from_r(X, R)
+    for i in range(X.shape[0]):
+        q = [Fraction(0)] * 4
+        for c in range(4):
+            e = Fraction(X[i, c]) - sum((q[k] * Fraction(R[k, c]) for k in range(c)), Fraction(0))
+            q[c] = e / Fraction(R[c, c])
+        assert all(Fraction(Q[i, c]) == q[c] for c in range(4))
+
+
+@pytest.mark.parametrize("n,k", [(4, 0), (8, 4), (16, 4)])
+def test_q_from_r_rebuilds_an_orthonormal_q(n, k):
+    """With the Householder R of a well-conditioned X, X R^{-1} has
+    orthonormal columns (to about kappa u) and Q R reproduces X."""
+    X = wl.svd_form(3000, n, wl.logspace_sigma(n, k), seed=60 + n)
+    R = oracle.householder_r(X)
+    Q = oracle.q_from_r(X, R)
+    assert np.linalg.norm(oracle.gram_dot2(Q) - np.eye(n)) <= 100 * EPS * 10.0 ** k
+    assert np.linalg.norm(Q @ R - X) <= 100 * EPS * np.linalg.norm(X)
+
+
+def test_q_from_r_rejects_singular_r():
+    R = np.triu(np.ones((3, 3)))
+    R[1, 1] = 0.0
+    with pytest.raises(RuntimeError):
+        oracle.q_from_r(np.ones((5, 3)), R)
