@@ -228,13 +228,16 @@ def main() -> int:
 
     if not args.no_compare:
         comp = {}
-        for name, fn in (("cholqr2", lambda: q.cholqr2_r(X)), ("svqb2", lambda: q.svqb(X, out=q.QLESS_SVQB_R))):
+        forms = (("cholqr2", lambda: q.cholqr2_r(X), 2), ("svqb2", lambda: q.svqb(X, out=q.QLESS_SVQB_R), 2),
+                 ("shifted_cholqr3", lambda: q.shifted_cholqr3_r(X), 3))
+        for name, fn, passes in forms:
             log("compare %s" % name)
             c_ms, _ = time_calls(fn, max(5, args.steps // 3), 2)
             res = fn()
             torch.cuda.synchronize()
             Rc = res[0].cpu().numpy()
-            comp[name] = {"ms": round(c_ms, 5), "GBps": round(gram2_bytes(m, n) / (c_ms * 1e-3) / 1e9, 1),
+            comp[name] = {"ms": round(c_ms, 5), "passes_over_X": passes,
+                          "GBps": round(passes * tsqr_bytes(m, n) / (c_ms * 1e-3) / 1e9, 1),
                           "e_R_vs_R0": float(np.linalg.norm(Rc - R0) / np.linalg.norm(R0)),
                           "info": int(res[-1].item())}
             log(json.dumps(comp[name]))
