@@ -18,6 +18,7 @@ Paper: Thies & Roehrig-Zoellner, arXiv 2603.20889.
                   paragraph of Sec. 3.1
   lstsq_from_r  : least squares via the Q-less R of [A b], Sec. 1
   q_from_r      : explicit Q = X R^{-1} rebuilt from X and the Q-less R, Sec. 1
+  two_phase_r   : R of (I - Y Y^T) X and B = Y^T X, the two-phase problem of Sec. 2
   gram_dot2     : X^T X in twice-working precision (error metric only)
 """
 from __future__ import annotations
@@ -68,6 +69,8 @@ def _load():
         lib.oracle_lstsq_from_r.restype = ctypes.c_int
         lib.oracle_q_from_r.argtypes = [dp, i64, i64, i64, dp, i64, dp, i64]
         lib.oracle_q_from_r.restype = ctypes.c_int
+        lib.oracle_two_phase_r.argtypes = [dp, i64, i64, dp, i64, i64, i64, dp, dp]
+        lib.oracle_two_phase_r.restype = ctypes.c_int
         lib.oracle_gram_dot2.argtypes = [dp, i64, i64, i64, dp]
         lib.oracle_gram_dot2.restype = None
         _lib = lib
@@ -175,6 +178,20 @@ def q_from_r(X, R) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("oracle_q_from_r failed: %d" % rc)
     return Q
+
+
+def two_phase_r(Y, X) -> tuple[np.ndarray, np.ndarray]:
+    """(B, R): B = Y^T X and R = R((I - Y Y^T) X) for Y (m x p) with
+    orthonormal columns."""
+    X, m, n, ldx = _as_rowmajor(X)
+    Y = np.ascontiguousarray(Y, dtype=np.float64).reshape(m, -1)
+    p = Y.shape[1]
+    B = np.empty((max(p, 1), n), dtype=np.float64)
+    R = np.empty((n, n), dtype=np.float64)
+    rc = _load().oracle_two_phase_r(_ptr(Y), p, max(p, 1), _ptr(X), m, n, ldx, _ptr(B), _ptr(R))
+    if rc != 0:
+        raise RuntimeError("oracle_two_phase_r failed: %d" % rc)
+    return B[:p], R
 
 
 def gram_dot2(X) -> np.ndarray:

@@ -18,6 +18,7 @@
  *   oracle_jacobi_eig     symmetric eigendecomposition (cyclic Jacobi, Golub & Van Loan Sec. 8.5) used by SVQB2
  *   oracle_lstsq_from_r   least squares from the Q-less R of [A b]   (Sec. 1, single-pass least squares)
  *   oracle_q_from_r       explicit Q = X R^{-1} rebuilt from the Q-less R (Sec. 1)
+ *   oracle_two_phase_r    R of (I - Y Y^T) X and B = Y^T X         (Sec. 2, the two-phase problem)
  *   oracle_gram_dot2      X^T X accumulated in twice-working precision (Ogita-Rump-Oishi Dot2), for the error metric
  *
  * Conventions
@@ -443,6 +444,36 @@ int oracle_q_from_r(const double *X, int64_t m, int64_t n, int64_t ldx, const do
         }
     }
     return 0;
+}
+
+/* ------------------------------------------- two-phase orthogonalisation */
+
+/* The "two-phase" problem named in Sec. 2: orthogonalise X (m x n) against
+ * an m x p Y with orthonormal columns and factor what is left,
+ * Q R = (I - Y Y^T) X.  B = Y^T X (p x n, pairwise sums over the m rows),
+ * Z = X - Y B row by row, R = R(Z) by oracle_householder_r.  B is row-major
+ * p x n (may be NULL when p == 0).  Returns what oracle_householder_r
+ * returns; -1 bad args, -2 no memory. */
+int oracle_two_phase_r(const double *Y, int64_t p, int64_t ldy, const double *X, int64_t m, int64_t n,
+                       int64_t ldx, double *B, double *R)
+{
+    if (n < 1 || m < 0 || p < 0 || R == NULL || (m > 0 && (X == NULL || ldx < n)) ||
+        (p > 0 && (B == NULL || (m > 0 && (Y == NULL || ldy < p)))))
+        return -1;
+    double *Z = (double *)malloc((size_t)((m > 0 ? m : 1) * n) * sizeof(double));
+    if (!Z) return -2;
+    for (int64_t a = 0; a < p; ++a)
+        for (int64_t c = 0; c < n; ++c)
+            B[a * n + c] = (m > 0) ? pdot(Y + a, ldy, X + c, ldx, m) : 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t c = 0; c < n; ++c) {
+            double z = X[i * ldx + c];
+            for (int64_t a = 0; a < p; ++a) z = z - Y[i * ldy + a] * B[a * n + c];
+            Z[i * n + c] = z;
+        }
+    int rc = oracle_householder_r(Z, m, n, n, R);
+    free(Z);
+    return rc;
 }
 
 /* ------------------------------------------------------ least squares */

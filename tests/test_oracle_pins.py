@@ -379,3 +379,46 @@ def test_q_from_r_rejects_singular_r():
     R[1, 1] = 0.0
     with pytest.raises(RuntimeError):
         oracle.q_from_r(np.ones((5, 3)), R)
+
+
+# ------------------------------------- two-phase orthogonalisation (Sec. 2)
+
+def test_two_phase_with_coordinate_basis_is_exact():
+    """Y = [e_1, e_2]: the projection zeroes the first two rows exactly, so
+    B is those rows and R is the Householder R of the rest, bit for bit."""
+    X = wl.dyadic(40, 5, seed=8)
+    Y = np.zeros((40, 2))
+    Y[0, 0] = Y[1, 1] = 1.0
+    B, R = oracle.two_phase_r(Y, X)
+    assert np.array_equal(B, X[:2])
+    Z = X.copy()
+    Z[:2] = 0.0
+    assert np.array_equal(R, oracle.householder_r(Z))
+
+
+def test_two_phase_without_basis_is_plain_r():
+    X = wl.gaussian(300, 6, seed=4)
+    B, R = oracle.two_phase_r(np.zeros((300, 0)), X)
+    assert B.shape == (0, 6)
+    assert np.array_equal(R, oracle.householder_r(X))
+
+
+@pytest.mark.parametrize("p,n,k", [(3, 4, 0), (8, 8, 4), (16, 5, 2)])
+def test_two_phase_recovers_known_parts(p, n, k):
+    """X = Y B0 + W R0 with [Y W] orthonormal: B = B0 and R = R0."""
+    g = wl.rng(90 + p + n)
+    U = wl.orthonormal_columns(2000, p + n, g)
+    Y, W = U[:, :p], U[:, p:]
+    B0 = g.standard_normal((p, n))
+    R0 = wl.triangular_with_singular_values(wl.logspace_sigma(n, k), g)
+    B, R = oracle.two_phase_r(Y, Y @ B0 + W @ R0)
+    assert np.linalg.norm(B - B0) <= 1e-13 * np.linalg.norm(B0)
+    assert oracle.rel_err_r(R, R0) <= 100 * EPS * max(1.0, 10.0 ** k)   # about kappa u
+
+
+def test_two_phase_of_a_vector_in_the_span_leaves_nothing():
+    g = wl.rng(7)
+    Y = wl.orthonormal_columns(1000, 4, g)
+    X = Y @ g.standard_normal((4, 3))
+    _, R = oracle.two_phase_r(Y, X)
+    assert np.linalg.norm(R) <= 1e-14 * np.linalg.norm(X)
