@@ -51,6 +51,18 @@ def test_config1_100000x4(gpu):
     check(X, run(X, gpu))
 
 
+def test_golden_fixtures(gpu):
+    """The stored values of tests/golden: the exact R of a tiny dyadic matrix
+    (the definition of Sec. 1) and the oracle's R of the 100000 x 4 workload."""
+    from test_golden import load_golden
+    print("case golden fixtures", flush=True)
+    g = load_golden("tiny_exact_r.txt")
+    R = run(g["X"], gpu)
+    assert oracle.rel_err_r(R, g["R"]) <= 64 * 2.0 ** -52 * np.linalg.cond(g["R"])
+    g1 = load_golden("config1_r.txt")
+    assert oracle.rel_err_r(run(wl.config1(), gpu), g1["R"]) <= E_R
+
+
 SHAPES = [
     (1, 1), (1, 4), (3, 8), (7, 8), (63, 1), (64, 2), (65, 3), (511, 4), (513, 5), (1000, 6), (4097, 7),
     (9999, 8), (12345, 9), (20000, 10), (3000, 12), (40001, 13), (50000, 16), (777, 17), (20000, 20),
