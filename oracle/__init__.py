@@ -11,6 +11,9 @@ Every function takes and returns numpy float64 arrays; X is row-major
 Paper: Thies & Roehrig-Zoellner, arXiv 2603.20889.
   householder_r : R of X, Sec. 1 (X = QR, R upper triangular), per-column
                   Householder reflector of Alg. 4 without the column pairing
+  householder_r_chunked : the same with every length-m sum in fixed
+                  64K-row chunks, OpenMP over chunks; bitwise independent
+                  of the thread count (for timing on all host cores)
   cholqr2_r     : Q-less Cholesky-QR2, Alg. 1
   shifted_cholqr3_r : Q-less shifted Cholesky-QR3, the robust variant Sec. 2
                   names (shift of Fukaya et al. 2020)
@@ -34,7 +37,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 GCC_FLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off",
-             "-fno-fast-math", "-fPIC", "-shared"]
+             "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = False) -> str:
@@ -57,6 +60,8 @@ def _load():
         i64 = ctypes.c_int64
         lib.oracle_householder_r.argtypes = [dp, i64, i64, i64, dp]
         lib.oracle_householder_r.restype = ctypes.c_int
+        lib.oracle_householder_r_chunked.argtypes = [dp, i64, i64, i64, dp, ctypes.c_int]
+        lib.oracle_householder_r_chunked.restype = ctypes.c_int
         lib.oracle_cholqr2_r.argtypes = [dp, i64, i64, i64, dp]
         lib.oracle_cholqr2_r.restype = ctypes.c_int
         lib.oracle_shifted_cholqr3_r.argtypes = [dp, i64, i64, i64, dp]
@@ -99,6 +104,17 @@ def householder_r(X) -> np.ndarray:
     rc = _load().oracle_householder_r(_ptr(X), m, n, ldx, _ptr(R))
     if rc != 0:
         raise RuntimeError("oracle_householder_r failed: %d" % rc)
+    return R
+
+
+def householder_r_chunked(X, threads: int = 1) -> np.ndarray:
+    """householder_r with chunked sums, on `threads` OpenMP threads; the
+    result does not depend on the thread count."""
+    X, m, n, ldx = _as_rowmajor(X)
+    R = np.empty((n, n), dtype=np.float64)
+    rc = _load().oracle_householder_r_chunked(_ptr(X), m, n, ldx, _ptr(R), int(threads))
+    if rc != 0:
+        raise RuntimeError("oracle_householder_r_chunked failed: %d" % rc)
     return R
 
 
@@ -211,6 +227,20 @@ def rel_err_r(R, R_ref) -> float:
     d = np.linalg.norm(R - R_ref)
     nr = np.linalg.norm(R_ref)
     return float(d / nr) if nr > 0 else float(d)
+
+
+def row_scaled_err(R, R_ref) -> float:
+    """max over i, j of |R - R_ref|_ij / |R_ref|_ii: each row's error against
+    that row's own scale, so a wrong small trailing row is seen even where
+    the normwise e_R is dominated by the large leading rows.  Rows of R_ref
+    with a zero diagonal are left out (rank-deficient inputs)."""
+    R = np.asarray(R, dtype=np.float64)
+    R_ref = np.asarray(R_ref, dtype=np.float64)
+    d = np.abs(np.diag(R_ref))
+    ok = d > 0
+    if not ok.any():
+        return 0.0
+    return float(np.max(np.abs(R - R_ref)[ok] / d[ok, None]))
 
 
 def gram_residual(X, R, G=None) -> float:

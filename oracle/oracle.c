@@ -12,6 +12,9 @@
  *
  * Contents (each function names the passage it follows):
  *   oracle_householder_r  R of X by unblocked Householder QR       (Sec. 1 problem statement; Alg. 4 per-column reflector)
+ *   oracle_householder_r_chunked  the same, every length-m sum cut into fixed
+ *                         64K-row chunks; OpenMP over chunks, bitwise the same
+ *                         result for any thread count (for timing on host cores)
  *   oracle_cholqr2_r      Q-less Cholesky-QR2                      (Sec. 3.1, Alg. 1)
  *   oracle_shifted_cholqr3_r  Q-less shifted Cholesky-QR3          (Sec. 2 related work; shift of Fukaya et al. 2020)
  *   oracle_svqb2          Q-less SVQB applied twice, QZ form         (Sec. 1 SVQB/QZ definition; Sec. 3.1 SVQB2 paragraph)
@@ -36,6 +39,7 @@
  * breakdown (see each function).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -127,6 +131,83 @@ int oracle_householder_r(const double *X, int64_t m, int64_t n, int64_t ldx, dou
     for (int64_t i = 0; i < n; ++i)
         for (int64_t c = 0; c < n; ++c) R[i * n + c] = (c >= i) ? A[c * M + i] : 0.0;
     free(A);
+    sign_normalise(R, n);
+    return 0;
+}
+
+/* ------------------------------------- chunked Householder QR (O7) */
+
+/* The same factorisation as oracle_householder_r, with every length-M sum
+ * taken in fixed chunks of CHUNK_ROWS terms: each chunk is summed pairwise
+ * (pdot), then the chunk totals are summed pairwise.  The chunk boundaries
+ * depend only on the length, never on the thread count, so OpenMP over the
+ * chunks (and over rows for the element-wise updates) gives bitwise the same
+ * R for any number of threads.  Exists so that the oracle can be timed on
+ * all host cores; the arithmetic per column is that of householder_colmajor. */
+#define CHUNK_ROWS 65536
+
+static double pairwise_array(const double *p, int64_t len)
+{
+    if (len <= 0) return 0.0;
+    if (len == 1) return p[0];
+    int64_t h = len / 2;
+    return pairwise_array(p, h) + pairwise_array(p + h, len - h);
+}
+
+/* sum_{i < len} a[i] b[i], chunked; part has room for ceil(len/CHUNK_ROWS). */
+static double chunked_dot(const double *a, const double *b, int64_t len, double *part)
+{
+    int64_t nc = (len + CHUNK_ROWS - 1) / CHUNK_ROWS;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t lo = c * CHUNK_ROWS;
+        int64_t cl = (len - lo < CHUNK_ROWS) ? len - lo : CHUNK_ROWS;
+        part[c] = pdot(a + lo, 1, b + lo, 1, cl);
+    }
+    return pairwise_array(part, nc);
+}
+
+int oracle_householder_r_chunked(const double *X, int64_t m, int64_t n, int64_t ldx, double *R, int nthreads)
+{
+    if (n < 1 || m < 0 || (m > 0 && (X == NULL || ldx < n)) || R == NULL || nthreads < 1)
+        return -1;
+    int64_t M = m > n ? m : n;
+    double *A = (double *)calloc((size_t)(M * n), sizeof(double));
+    double *part = (double *)malloc((size_t)((M + CHUNK_ROWS - 1) / CHUNK_ROWS + 1) * sizeof(double));
+    if (!A || !part) { free(A); free(part); return -2; }
+    int saved = omp_get_max_threads();
+    omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) A[j * M + i] = X[i * ldx + j];
+    for (int64_t j = 0; j < n; ++j) {
+        double *a = A + j * M;
+        double alpha = a[j];
+        int64_t below = M - j - 1;
+        double s = chunked_dot(a + j + 1, a + j + 1, below, part);
+        if (s == 0.0)
+            continue;
+        double norm = sqrt(alpha * alpha + s);
+        double beta = (alpha >= 0.0) ? -norm : norm;
+        double scale = 1.0 / (alpha - beta);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = j + 1; i < M; ++i) a[i] = a[i] * scale;
+        double tau = (beta - alpha) / beta;
+        a[j] = beta;
+        for (int64_t c = j + 1; c < n; ++c) {
+            double *ac = A + c * M;
+            double w = ac[j] + chunked_dot(a + j + 1, ac + j + 1, below, part);
+            double tw = tau * w;
+            ac[j] = ac[j] - tw;
+#pragma omp parallel for schedule(static)
+            for (int64_t i = j + 1; i < M; ++i) ac[i] = ac[i] - tw * a[i];
+        }
+    }
+    omp_set_num_threads(saved);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < n; ++c) R[i * n + c] = (c >= i) ? A[c * M + i] : 0.0;
+    free(A);
+    free(part);
     sign_normalise(R, n);
     return 0;
 }

@@ -155,3 +155,109 @@ def test_shifted_battery_rejects_mutant(tmp_path, name):
     lib = build_shifted_mutant(tmp_path, name)
     with np.errstate(all="ignore"):
         assert not shifted_pins_pass(lambda X: shifted_mutant_r(lib, X)), name
+
+
+# Dot2 Gram (the reference X^T X of the Gram-residual metric): mistakes
+# planted inside oracle_gram_dot2 only; the pin is the Dot2 error bound
+# against the exact rational X^T X.
+MUTANTS_DOT2 = {
+    "drop_two_product_error": ("s = s + (q + r);", "s = s + q;"),
+    "drop_two_sum_error": ("s = s + (q + r);", "s = s + r;"),
+    "plain_product_sum": ("two_sum(p, h, &p, &q);", "p = p + h; q = 0.0;"),
+}
+
+
+def build_dot2_mutant(tmp_path, name):
+    old, new = MUTANTS_DOT2[name]
+    src = open(SRC).read()
+    start = src.index("void oracle_gram_dot2(")
+    body = src[start:]
+    assert body.count(old) >= 1, name
+    src = src[:start] + body.replace(old, new, 1)
+    c = tmp_path / ("%s.c" % name)
+    so = tmp_path / ("%s.so" % name)
+    c.write_text(src)
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-w", str(c), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_gram_dot2.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp]
+    lib.oracle_gram_dot2.restype = None
+    return lib
+
+
+def dot2_mutant_gram(lib, X):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    C = np.empty((n, n))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_gram_dot2(X.ctypes.data_as(dp), m, n, n, C.ctypes.data_as(dp))
+    return C
+
+
+def dot2_pins_pass(gram_of) -> bool:
+    from test_oracle_pins import dot2_pin_inputs, dot2_violations
+    return all(dot2_violations(gram_of(X), X) == [] for X in dot2_pin_inputs())
+
+
+def test_dot2_battery_accepts_real_oracle():
+    assert dot2_pins_pass(oracle.gram_dot2)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_DOT2))
+def test_dot2_battery_rejects_mutant(tmp_path, name):
+    lib = build_dot2_mutant(tmp_path, name)
+    assert not dot2_pins_pass(lambda X: dot2_mutant_gram(lib, X)), name
+
+
+# Chunked Householder variant: mistakes planted inside its own code.
+MUTANTS_CHUNKED = {
+    "chunk_tail_dropped": ("int64_t cl = (len - lo < CHUNK_ROWS) ? len - lo : CHUNK_ROWS;",
+                           "int64_t cl = CHUNK_ROWS < len - lo ? CHUNK_ROWS : 0;"),
+    "chunk_totals_lose_last": ("return pairwise_array(part, nc);", "return pairwise_array(part, nc - 1);"),
+    "chunked_pivot_term_dropped": ("double w = ac[j] + chunked_dot(", "double w = chunked_dot("),
+}
+
+
+def build_chunked_mutant(tmp_path, name):
+    old, new = MUTANTS_CHUNKED[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    src = src.replace(old, new, 1)
+    c = tmp_path / ("%s.c" % name)
+    so = tmp_path / ("%s.so" % name)
+    c.write_text(src)
+    subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-w", str(c), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_householder_r_chunked.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp,
+                                                 ctypes.c_int]
+    lib.oracle_householder_r_chunked.restype = ctypes.c_int
+    return lib
+
+
+def chunked_pins_pass(r_of) -> bool:
+    Xk, R0 = wl.known_r(150_000, 5, wl.logspace_sigma(5, 3), seed=3)
+    Rk = r_of(Xk)
+    if not np.all(np.isfinite(Rk)) or oracle.rel_err_r(Rk, R0) > 1e-12:
+        return False
+    Xg = wl.gaussian(70_001, 4, seed=8)
+    return oracle.rel_err_r(r_of(Xg), lapack_r(Xg)) <= 1e-13
+
+
+def test_chunked_battery_accepts_real_oracle():
+    assert chunked_pins_pass(lambda X: oracle.householder_r_chunked(X, threads=2))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_CHUNKED))
+def test_chunked_battery_rejects_mutant(tmp_path, name):
+    lib = build_chunked_mutant(tmp_path, name)
+
+    def r_of(X):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        m, n = X.shape
+        R = np.empty((n, n))
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_householder_r_chunked(X.ctypes.data_as(dp), m, n, n, R.ctypes.data_as(dp), 2)
+        return R
+    with np.errstate(all="ignore"):
+        assert not chunked_pins_pass(r_of), name

@@ -122,6 +122,85 @@ def test_gram_invariant_holds_with_extended_gram():
     assert oracle.gram_residual(X, R) <= 1e-14
 
 
+def exact_gram(X: np.ndarray):
+    """X^T X in exact rational arithmetic (every double is a dyadic rational,
+    so every product and sum is exact as a Fraction)."""
+    m, n = X.shape
+    F = [[Fraction(float(v)) for v in row] for row in X]
+    return [[sum((F[i][a] * F[i][b] for i in range(m)), Fraction(0)) for b in range(n)] for a in range(n)]
+
+
+def dot2_violations(C: np.ndarray, X: np.ndarray) -> list:
+    """Entries of C that break the Dot2 error bound of Ogita, Rump and Oishi
+    (2005, Prop. 5.5): |res - x^T y| <= u |x^T y| + gamma_{m}^2 |x|^T |y| with
+    u = 2^-53 and gamma_m = m u / (1 - m u) -- the bound of a dot product
+    computed in twice the working precision and rounded once."""
+    m, n = X.shape
+    u = 2.0 ** -53
+    gam = m * u / (1.0 - m * u)
+    Cx = exact_gram(X)
+    A = np.abs(X).T @ np.abs(X)
+    bad = []
+    for a in range(n):
+        for b in range(n):
+            err = abs(Fraction(float(C[a, b])) - Cx[a][b])
+            bound = Fraction(u) * abs(Cx[a][b]) + Fraction(gam * gam * 1.01 * float(A[a, b]))
+            if err > bound:
+                bad.append((a, b, float(err), float(bound)))
+    return bad
+
+
+def dot2_pin_inputs():
+    """Inputs for the Dot2 pin: (1) iid N(0,1) entries with full 53-bit
+    mantissas; (2) rows in pairs (a, b), (-a, b + t) with t ~ 1e-9, so the
+    off-diagonal sum cancels to about 1e-9 of its terms -- a sum of rounded
+    products then carries an error many orders above the Dot2 bound."""
+    g = wl.rng(4242)
+    X1 = g.standard_normal((1500, 3))
+    a = g.standard_normal(1000)
+    b = g.standard_normal(1000)
+    t = 1e-9 * g.standard_normal(1000)
+    X2 = np.empty((2000, 2))
+    X2[0::2, 0], X2[0::2, 1] = a, b
+    X2[1::2, 0], X2[1::2, 1] = -a, b + t
+    return [X1, X2]
+
+
+def test_gram_dot2_is_twice_working_precision():
+    """The Gram matrix behind the e_G metric: every entry of the oracle's
+    Dot2 X^T X is within the Dot2 bound of the exact rational X^T X, on
+    generic data and on data whose off-diagonal sum cancels almost fully."""
+    for X in dot2_pin_inputs():
+        C = oracle.gram_dot2(X)
+        assert dot2_violations(C, X) == []
+    # the cancelling case is one that plain float64 accumulation gets wrong
+    X = dot2_pin_inputs()[1]
+    assert dot2_violations(X.T @ X, X) != []
+
+
+# ------------------------------------------------ chunked variant (O7)
+
+@pytest.mark.parametrize("m,n", [(1, 3), (5, 8), (65536, 2), (65537, 3), (300_001, 5), (200_000, 16)])
+def test_chunked_is_independent_of_threads_and_matches(m, n):
+    """The chunked oracle gives bitwise the same R on 1, 3 and 8 threads, and
+    agrees with the plain oracle and LAPACK (only the summation order of the
+    length-m sums differs)."""
+    X = wl.gaussian(m, n, seed=m + 17 * n)
+    R1 = oracle.householder_r_chunked(X, threads=1)
+    for t in (3, 8):
+        assert np.array_equal(oracle.householder_r_chunked(X, threads=t), R1)
+    assert oracle.rel_err_r(R1, oracle.householder_r(X)) <= 1e-14
+    assert oracle.rel_err_r(R1, lapack_r(X)) <= 1e-13
+
+
+def test_chunked_known_r_and_exact():
+    Xk, R0 = wl.known_r(150_000, 6, wl.logspace_sigma(6, 4), seed=71)
+    assert oracle.rel_err_r(oracle.householder_r_chunked(Xk, threads=4), R0) <= 1e-12
+    X = wl.dyadic(9, 3, seed=5)
+    Rf = np.array([[float(v) for v in row] for row in exact_r_via_gram(X)])
+    assert oracle.rel_err_r(oracle.householder_r_chunked(X, threads=2), Rf) <= 1e-13
+
+
 # --------------------------------------------------- special structure
 
 @pytest.mark.parametrize("n,extra", [(4, 0), (8, 5), (16, 100), (33, 1)])
