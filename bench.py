@@ -85,6 +85,25 @@ def load_traffic(workload: str):
     return d.get("traffic_bytes_per_launch")
 
 
+def host_threads():
+    """(threads the CPU oracle runs on, cores this process may use): the
+    cores in this process's affinity mask, capped by OMP_NUM_THREADS when it
+    is set (the host's CPU share for this GPU)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    use = min(avail, int(cap)) if cap.isdigit() and int(cap) > 0 else avail
+    return max(1, use), avail
+
+
+def timed(fn):
+    t0 = time.perf_counter()
+    r = fn()
+    return r, time.perf_counter() - t0
+
+
 def time_calls(fn, steps: int, warmup: int):
     import torch
     for _ in range(warmup):
@@ -212,18 +231,31 @@ def main() -> int:
     out["plain_read_reference"] = {"kernel": "torch.sum over X", "ms": round(rd_ms, 5),
                                    "GBps": round(nbytes / (rd_ms * 1e-3) / 1e9, 1)}
 
+    cpu_threads = None
     if not args.no_cpu:
         import oracle
-        log("CPU oracle on the same matrix (host copy)")
+        cpu_threads, cpu_avail = host_threads()
+        log("CPU oracle on the same matrix (host copy), 1 and %d threads" % cpu_threads)
         Xh = X.cpu().numpy()
-        t0 = time.perf_counter()
-        Ro = oracle.householder_r(Xh)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
-                               "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "the full %d x %d benchmark matrix, one call of the "
-                                         "single-threaded oracle" % (m, n)}
-        out["accuracy"]["e_R_vs_oracle"] = float(np.linalg.norm(R.cpu().numpy() - Ro) / np.linalg.norm(Ro))
+        R1, t1 = timed(lambda: oracle.householder_r_chunked(Xh, 1))
+        RN, tN = timed(lambda: oracle.householder_r_chunked(Xh, cpu_threads))
+        c1 = wl.config1()
+        c1_1 = min(timed(lambda: oracle.householder_r_chunked(c1, 1))[1] for _ in range(3))
+        c1_N = min(timed(lambda: oracle.householder_r_chunked(c1, cpu_threads))[1] for _ in range(3))
+        out["cpu_baseline"] = {
+            "value": round(nbytes / tN / 1e9, 4), "unit": "GB/s", "cores": cpu_threads,
+            "cores_available": cpu_avail, "kind": "oracle", "seconds": round(tN, 3),
+            "sample": "the full %d x %d benchmark matrix, one call of the oracle with its length-m sums in "
+                      "fixed 64K-row chunks (OpenMP over chunks, result bitwise independent of the thread "
+                      "count), on %d host threads" % (m, n, cpu_threads),
+            "single_thread": {"value": round(nbytes / t1 / 1e9, 4), "unit": "GB/s", "seconds": round(t1, 3)},
+            "bitwise_equal_1_vs_all_threads": bool(np.array_equal(R1, RN)),
+            "config1_100000x4": {"seconds_1_thread": round(c1_1, 5), "seconds_all_threads": round(c1_N, 5),
+                                 "GBps_1_thread": round(c1.nbytes / c1_1 / 1e9, 4),
+                                 "GBps_all_threads": round(c1.nbytes / c1_N / 1e9, 4)},
+        }
+        out["accuracy"]["e_R_vs_oracle"] = float(np.linalg.norm(R.cpu().numpy() - RN) / np.linalg.norm(RN))
+        log("cpu: %s" % json.dumps(out["cpu_baseline"]))
         del Xh
 
     if not args.no_compare:
@@ -261,7 +293,8 @@ def main() -> int:
 
     if not args.no_sweep:
         out["sweep"] = bench_sweep(q, wl, dev, log, [int(v) for v in args.ns.split(",") if v],
-                                   ks=tuple(int(v) for v in args.sweep_ks.split(",") if v))
+                                   ks=tuple(int(v) for v in args.sweep_ks.split(",") if v),
+                                   cpu_threads=cpu_threads)
 
     if not args.no_batched:
         out["batched"] = bench_batched(q, wl, dev, log)
@@ -272,11 +305,18 @@ def main() -> int:
     return 0
 
 
-def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8)):
+# CPU oracle timing in the sweep (k = 4): all host threads up to this n, one
+# thread up to the smaller one -- together about 15 s of host work at 16 threads.
+CPU_SWEEP_MAX_N_ALL = 32
+CPU_SWEEP_MAX_N_ONE = 8
+
+
+def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads=None):
     """Column sweep m = 2^25, n in ns, sigma log-spaced to 10^-k, k in ks
     (default {0, 4, 8}): accuracy of TSQR and CholQR2 for every (n, k); timing
     (k = 4) of the TSQR launch (HIP events around it) and of the whole
-    CholQR2 call."""
+    CholQR2 call; with cpu_threads, the CPU oracle (chunked sums) on the same
+    matrix for the smaller n."""
     import numpy as np
     import torch
     sweep = []
@@ -329,6 +369,16 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8)):
                             "cholqr2_GBps": round(gram2_bytes(m, ns) / (c_ms * 1e-3) / 1e9, 1),
                             "cholqr2_TFps": round(5.0 * m * ns * ns / (c_ms * 1e-3) / 1e12, 2)})
                 del flush
+                if cpu_threads and ns <= CPU_SWEEP_MAX_N_ALL:
+                    import oracle
+                    Xh = Xs.cpu().numpy()
+                    _, tN = timed(lambda: oracle.householder_r_chunked(Xh, cpu_threads))
+                    rec["cpu_oracle_GBps_all_threads"] = round(tsqr_bytes(m, ns) / tN / 1e9, 4)
+                    rec["cpu_oracle_threads"] = cpu_threads
+                    if ns <= CPU_SWEEP_MAX_N_ONE:
+                        _, t1 = timed(lambda: oracle.householder_r_chunked(Xh, 1))
+                        rec["cpu_oracle_GBps_1_thread"] = round(tsqr_bytes(m, ns) / t1 / 1e9, 4)
+                    del Xh
             del Xs, ws
             torch.cuda.empty_cache()
         sweep.append(rec)

@@ -57,7 +57,8 @@ typedef enum {
     QLESS_METHOD_CHOLQR2 = 1,    /* cholqr2_r */
     QLESS_METHOD_SVQB = 2,       /* svqb */
     QLESS_METHOD_TSQR_UPDATE = 3, /* qless_tsqr_r_update */
-    QLESS_METHOD_SHIFTED_CHOLQR3 = 4 /* shifted_cholqr3_r */
+    QLESS_METHOD_SHIFTED_CHOLQR3 = 4, /* shifted_cholqr3_r */
+    QLESS_METHOD_Q_FROM_R = 5     /* qless_q_from_r */
 } qless_method;
 
 typedef enum {
@@ -159,6 +160,60 @@ int shifted_cholqr3_r(const double *X, int64_t m, int64_t n, int64_t ldx,
 int svqb(const double *X, int64_t m, int64_t n, int64_t ldx, int out,
          double *Z_or_R, int64_t ldz, double *sigma, double trunc_tol,
          int32_t *info, void *work, size_t work_bytes, hipStream_t stream);
+
+/*
+ * svqb_q -- SVQB2 with the explicit Q (the variant that stores Q, compared
+ * with the Q-less one in Sec. 4.6, Fig. 3): the two Gram passes of svqb,
+ * then one more streaming pass Q = X D1 D2 with D2 = U2 L2^{-1/2}, so that
+ * X = Q Z with Q^T Q = I up to rounding (for truncated eigenvalues the
+ * corresponding columns of Q are zero).  Q: device, m x n row-major, ldq >= n,
+ * must not overlap X.  Z, sigma, trunc_tol and info as for svqb with
+ * out = QLESS_SVQB_QZ; workspace from qless_workspace_bytes(QLESS_METHOD_SVQB,
+ * m, n).  Three passes over X, one over Q (8mn bytes written).
+ */
+int svqb_q(const double *X, int64_t m, int64_t n, int64_t ldx, double *Q, int64_t ldq,
+           double *Z, int64_t ldz, double *sigma, double trunc_tol, int32_t *info,
+           void *work, size_t work_bytes, hipStream_t stream);
+
+/*
+ * qless_q_from_r -- the explicit Q = X R^{-1} rebuilt from X and its Q-less R
+ * (Sec. 1: Q is not stored, and can be recovered from X and R afterwards
+ * when X is well conditioned).  R^{-1} is formed once on the device (one
+ * workgroup), then X is streamed once: Q = X R^{-1} row by row (8mn bytes
+ * read, 8mn written; the zero blocks of the triangular R^{-1} are skipped).
+ *
+ * R: device, n x n upper triangular (ldr >= n; entries below the diagonal
+ * are ignored; any diagonal signs).  Q: device, m x n row-major, ldq >= n,
+ * must not overlap X.  info (device int32, may be NULL): 0, or j (1..n) if
+ * R_jj == 0 -- then every entry of Q is NaN.  Workspace from
+ * qless_workspace_bytes(QLESS_METHOD_Q_FROM_R, m, n).  Orthonormality of Q
+ * degrades with the condition number of X (about kappa^2 u for the R of a
+ * Householder TSQR).
+ */
+int qless_q_from_r(const double *X, int64_t m, int64_t n, int64_t ldx, const double *R, int64_t ldr,
+                   double *Q, int64_t ldq, int32_t *info, void *work, size_t work_bytes,
+                   hipStream_t stream);
+
+/*
+ * qless_two_phase_r -- the two-phase problem of Sec. 2 in one streaming pass:
+ * for Y (m x p, orthonormal columns) and X (m x n), B = Y^T X and the Q-less
+ * R of the projected block, Q R = (I - Y Y^T) X.  One Q-less TSQR of the
+ * concatenation [Y X] (read from the two pointers; never formed) gives
+ * R([Y X]) = [[I, B], [0, R]] up to rounding, because Y's own R is the
+ * identity; Y and X are each read once.  Y must have orthonormal columns to
+ * working precision (else B is Q1^T X for the Q1 of Y = Q1 R11).
+ *
+ * Y: device, m x p row-major, ldy >= p (may be NULL when p == 0 or m == 0);
+ * p >= 0, n >= 1, p + n <= QLESS_MAX_N (else QLESS_ERR_UNSUPPORTED).
+ * X: device, m x n row-major, ldx >= n.  B: device, p x n row-major,
+ * ldb >= n (may be NULL when p == 0).  R: device, n x n, ldr >= n, diagonal
+ * >= 0.  B and R must not overlap Y or X.  Workspace of
+ * qless_two_phase_workspace_bytes(m, p, n) bytes (0 for invalid sizes).
+ */
+size_t qless_two_phase_workspace_bytes(int64_t m, int64_t p, int64_t n);
+int qless_two_phase_r(const double *Y, int64_t p, int64_t ldy, const double *X, int64_t m, int64_t n,
+                      int64_t ldx, double *B, int64_t ldb, double *R, int64_t ldr, void *work,
+                      size_t work_bytes, hipStream_t stream);
 
 /*
  * qless_lstsq_finish -- least squares from the Q-less R of [A b] (Sec. 1):

@@ -28,6 +28,7 @@ QLESS_METHOD_TSQR_UPDATE = 3
 QLESS_METHOD_CHOLQR2 = 1
 QLESS_METHOD_SVQB = 2
 QLESS_METHOD_SHIFTED_CHOLQR3 = 4
+QLESS_METHOD_Q_FROM_R = 5
 
 QLESS_SVQB_R = 0
 QLESS_SVQB_QZ = 1
@@ -39,7 +40,8 @@ EXPORTED = (
     "cholqr2_r", "shifted_cholqr3_r", "svqb", "qless_lstsq_finish", "qless_timing_enable", "qless_timing_reset",
     "qless_timing_read", "qless_batch_plan_create", "qless_batch_plan_destroy",
     "qless_batch_plan_workspace_bytes", "qless_batch_plan_tiles", "qless_batch_plan_upload",
-    "qless_tsqr_r_batched", "qless_tune_set", "qless_tune_get",
+    "qless_tsqr_r_batched", "qless_tune_set", "qless_tune_get", "qless_q_from_r", "svqb_q",
+    "qless_two_phase_r", "qless_two_phase_workspace_bytes",
 )
 
 
@@ -85,6 +87,14 @@ def load() -> ctypes.CDLL:
     lib.shifted_cholqr3_r.restype = ctypes.c_int
     lib.svqb.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, i64, vp, dbl, vp, vp, sz, vp]
     lib.svqb.restype = ctypes.c_int
+    lib.qless_q_from_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp]
+    lib.qless_q_from_r.restype = ctypes.c_int
+    lib.svqb_q.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, vp, dbl, vp, vp, sz, vp]
+    lib.svqb_q.restype = ctypes.c_int
+    lib.qless_two_phase_workspace_bytes.argtypes = [i64, i64, i64]
+    lib.qless_two_phase_workspace_bytes.restype = sz
+    lib.qless_two_phase_r.argtypes = [vp, i64, i64, vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp]
+    lib.qless_two_phase_r.restype = ctypes.c_int
     lib.qless_lstsq_finish.argtypes = [vp, i64, i64, vp, vp, vp, vp]
     lib.qless_lstsq_finish.restype = ctypes.c_int
     lib.qless_batch_plan_create.argtypes = [ctypes.POINTER(qless_matrix_desc), i32, i64, i32,
@@ -140,10 +150,41 @@ def _matrix(X, name="X"):
     if X.device.type != "cuda":
         raise TypeError("%s must live on a GPU (got %s)" % (name, X.device))
     m, n = X.shape
-    if m > 0 and X.stride(1) != 1:
+    # rows must be contiguous and must not overlap (an expanded or
+    # transposed view would make the kernels read past the allocation)
+    if m > 0 and (X.stride(1) != 1 or (m > 1 and X.stride(0) < n)):
         X = X.contiguous()
     ldx = X.stride(0) if m > 1 else n
     return X, int(m), int(n), int(max(ldx, n))
+
+
+def _out(T, rows: int, cols: int, device, name: str, dtype=None):
+    """Check a caller-supplied output tensor before any launch: the dtype
+    (float64 unless given), X's device, at least rows x cols (a vector when
+    rows == 0), unit stride along a row and non-overlapping rows."""
+    import torch
+    dtype = dtype or torch.float64
+    if not isinstance(T, torch.Tensor) or T.dtype != dtype:
+        raise TypeError("%s must be a torch.%s tensor" % (name, str(dtype).replace("torch.", "")))
+    if T.device != device:
+        raise ValueError("%s must live on %s (got %s)" % (name, device, T.device))
+    if rows == 0:
+        if T.dim() != 1 or T.numel() < cols or (cols > 1 and T.stride(0) != 1):
+            raise ValueError("%s must be a contiguous vector of at least %d elements" % (name, cols))
+        return T
+    if T.dim() != 2 or T.shape[0] < rows or T.shape[1] < cols:
+        raise ValueError("%s must be at least %d x %d (got %s)" % (name, rows, cols, tuple(T.shape)))
+    if T.stride(1) != 1 or (T.shape[0] > 1 and T.stride(0) < cols):
+        raise ValueError("%s must have unit column stride and rows at least %d apart" % (name, cols))
+    return T
+
+
+def _work_arg(work, device):
+    """Caller-supplied workspace: a device tensor; returns its size in bytes."""
+    import torch
+    if not isinstance(work, torch.Tensor) or work.device != device or not work.is_contiguous():
+        raise ValueError("work must be a contiguous tensor on %s" % device)
+    return work.numel() * work.element_size()
 
 
 def _stream(device):
@@ -172,10 +213,12 @@ def qless_tsqr_r(X, R=None, work=None):
     with torch.cuda.device(dev):
         if R is None:
             R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(R, n, n, dev, "R")
         if work is None:
             work, wb = _workspace(QLESS_METHOD_TSQR, m, n, dev)
         else:
-            wb = work.numel() * work.element_size()
+            wb = _work_arg(work, dev)
         st = load().qless_tsqr_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
                                  ctypes.c_void_p(R.data_ptr()), R.stride(0),
                                  ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb,
@@ -189,11 +232,12 @@ def qless_tsqr_r_update(X, R, work=None):
     import torch
     X, m, n, ldx = _matrix(X)
     dev = X.device
+    _out(R, n, n, dev, "R")
     with torch.cuda.device(dev):
         if work is None:
             work, wb = _workspace(QLESS_METHOD_TSQR_UPDATE, m, n, dev)
         else:
-            wb = work.numel() * work.element_size()
+            wb = _work_arg(work, dev)
         st = load().qless_tsqr_r_update(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
                                         ctypes.c_void_p(R.data_ptr()), R.stride(0),
                                         ctypes.c_void_p(work.data_ptr()), wb, _stream(dev))
@@ -210,12 +254,16 @@ def cholqr2_r(X, R=None, info=None, work=None):
     with torch.cuda.device(dev):
         if R is None:
             R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(R, n, n, dev, "R")
         if info is None:
             info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
         if work is None:
             work, wb = _workspace(QLESS_METHOD_CHOLQR2, m, n, dev)
         else:
-            wb = work.numel() * work.element_size()
+            wb = _work_arg(work, dev)
         st = load().cholqr2_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
                               ctypes.c_void_p(R.data_ptr()), R.stride(0), ctypes.c_void_p(info.data_ptr()),
                               ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
@@ -232,12 +280,16 @@ def shifted_cholqr3_r(X, R=None, info=None, work=None):
     with torch.cuda.device(dev):
         if R is None:
             R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(R, n, n, dev, "R")
         if info is None:
             info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
         if work is None:
             work, wb = _workspace(QLESS_METHOD_SHIFTED_CHOLQR3, m, n, dev)
         else:
-            wb = work.numel() * work.element_size()
+            wb = _work_arg(work, dev)
         st = load().shifted_cholqr3_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
                                       ctypes.c_void_p(R.data_ptr()), R.stride(0), ctypes.c_void_p(info.data_ptr()),
                                       ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
@@ -253,14 +305,20 @@ def svqb(X, out: int = QLESS_SVQB_R, trunc_tol: float = 0.0, Z=None, sigma=None,
     with torch.cuda.device(dev):
         if Z is None:
             Z = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(Z, n, n, dev, "Z")
         if sigma is None:
             sigma = torch.empty(n, dtype=torch.float64, device=dev)
+        else:
+            _out(sigma, 0, n, dev, "sigma")
         if info is None:
             info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
         if work is None:
             work, wb = _workspace(QLESS_METHOD_SVQB, m, n, dev)
         else:
-            wb = work.numel() * work.element_size()
+            wb = _work_arg(work, dev)
         st = load().svqb(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx, int(out),
                          ctypes.c_void_p(Z.data_ptr()), Z.stride(0), ctypes.c_void_p(sigma.data_ptr()),
                          float(trunc_tol), ctypes.c_void_p(info.data_ptr()),
@@ -269,19 +327,128 @@ def svqb(X, out: int = QLESS_SVQB_R, trunc_tol: float = 0.0, Z=None, sigma=None,
     return Z, sigma, info
 
 
+def qless_q_from_r(X, R, Q=None, info=None, work=None):
+    """Explicit Q = X R^{-1} (m x n) from X and an upper-triangular R, one
+    streaming pass (Sec. 1).  Returns (Q, info): info = j when R_jj == 0
+    (Q is NaN then)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    R, _, nr, ldr = _matrix(R, "R")
+    if R.shape[0] != n or nr != n or R.device != dev:
+        raise ValueError("R must be an n x n matrix on X's device")
+    with torch.cuda.device(dev):
+        if Q is None:
+            Q = torch.empty((m, n), dtype=torch.float64, device=dev)
+        else:
+            _out(Q, m, n, dev, "Q")
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_Q_FROM_R, m, n, dev)
+        else:
+            wb = _work_arg(work, dev)
+        st = load().qless_q_from_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                                   ctypes.c_void_p(R.data_ptr()), ldr,
+                                   ctypes.c_void_p(Q.data_ptr() if m else 0), Q.stride(0) if m > 1 else n,
+                                   ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(work.data_ptr()), wb,
+                                   _stream(dev))
+    _check(st, "qless_q_from_r")
+    return Q, info
+
+
+def svqb_q(X, Q=None, Z=None, sigma=None, info=None, trunc_tol: float = 0.0, work=None):
+    """SVQB2 with the explicit Q: X = Q Z, Q = X D1 D2.  Returns
+    (Q, Z, sigma, info)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if Q is None:
+            Q = torch.empty((m, n), dtype=torch.float64, device=dev)
+        else:
+            _out(Q, m, n, dev, "Q")
+        if Z is None:
+            Z = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(Z, n, n, dev, "Z")
+        if sigma is None:
+            sigma = torch.empty(n, dtype=torch.float64, device=dev)
+        else:
+            _out(sigma, 0, n, dev, "sigma")
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_SVQB, m, n, dev)
+        else:
+            wb = _work_arg(work, dev)
+        st = load().svqb_q(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                           ctypes.c_void_p(Q.data_ptr() if m else 0), Q.stride(0) if m > 1 else n,
+                           ctypes.c_void_p(Z.data_ptr()), Z.stride(0), ctypes.c_void_p(sigma.data_ptr()),
+                           float(trunc_tol), ctypes.c_void_p(info.data_ptr()),
+                           ctypes.c_void_p(work.data_ptr() if work is not None else 0), wb, _stream(dev))
+    _check(st, "svqb_q")
+    return Q, Z, sigma, info
+
+
+def qless_two_phase_r(Y, X, B=None, R=None, work=None):
+    """Two-phase orthogonalisation in one pass (Sec. 2): B = Y^T X (p x n) and
+    R = R((I - Y Y^T) X) (n x n) for Y with orthonormal columns."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    Y, my, p, ldy = _matrix(Y, "Y")
+    if my != m or Y.device != dev:
+        raise ValueError("Y must have X's rows and live on X's device")
+    with torch.cuda.device(dev):
+        if B is None:
+            B = torch.empty((p, n), dtype=torch.float64, device=dev)
+        elif p > 0:
+            _out(B, p, n, dev, "B")
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(R, n, n, dev, "R")
+        nbytes = int(load().qless_two_phase_workspace_bytes(m, p, n))
+        if work is None:
+            work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+            wb = work.numel()
+        else:
+            wb = _work_arg(work, dev)
+        st = load().qless_two_phase_r(ctypes.c_void_p(Y.data_ptr() if p and m else 0), p, ldy,
+                                      ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                                      ctypes.c_void_p(B.data_ptr() if p else 0), B.stride(0) if p > 1 else n,
+                                      ctypes.c_void_p(R.data_ptr()), R.stride(0),
+                                      ctypes.c_void_p(work.data_ptr()), wb, _stream(dev))
+    _check(st, "qless_two_phase_r")
+    return B, R
+
+
 def qless_lstsq_finish(Rt, x=None, resid=None, info=None):
     """x and |rho| from R([A b]) on the device (back substitution)."""
     import torch
     Rt, k, k2, ldr = _matrix(Rt, "Rt")
+    if k != k2 or k < 2:
+        raise ValueError("Rt must be a square (n+1) x (n+1) matrix with n >= 1 (got %d x %d)" % (k, k2))
     n = k - 1
     dev = Rt.device
     with torch.cuda.device(dev):
         if x is None:
             x = torch.empty(n, dtype=torch.float64, device=dev)
+        else:
+            _out(x, 0, n, dev, "x")
         if resid is None:
             resid = torch.empty(1, dtype=torch.float64, device=dev)
+        else:
+            _out(resid, 0, 1, dev, "resid")
         if info is None:
             info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
         st = load().qless_lstsq_finish(ctypes.c_void_p(Rt.data_ptr()), n, ldr, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(info.data_ptr()),
                                        _stream(dev))
@@ -313,7 +480,8 @@ class BatchPlan:
             X, m, n, ldx = _matrix(X)
             if X.device != self.device:
                 raise ValueError("all matrices must be on one device")
-            R = Rs[i] if Rs is not None else torch.zeros((n, n), dtype=torch.float64, device=self.device)
+            R = _out(Rs[i], n, n, self.device, "Rs[%d]" % i) if Rs is not None else \
+                torch.zeros((n, n), dtype=torch.float64, device=self.device)
             self.Xs.append(X)
             self.Rs.append(R)
             descs[i] = qless_matrix_desc(X.data_ptr() if m else 0, m, n, ldx, R.data_ptr(), R.stride(0),

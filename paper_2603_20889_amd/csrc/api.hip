@@ -148,13 +148,8 @@ const char* qless_status_string(int status) {
 
 const char* qless_version(void) { return "qless 0.1 gfx950"; }
 
-static int check_matrix_args(const void* X, int64_t m, int64_t n, int64_t ldx, const void* R, int64_t ldr) {
-    if (n < 1 || m < 0) return QLESS_ERR_ARG;
-    if (n > QLESS_MAX_N) return QLESS_ERR_UNSUPPORTED;
-    if (R == nullptr || ldr < n) return QLESS_ERR_ARG;
-    if (m > 0 && (X == nullptr || ldx < n)) return QLESS_ERR_ARG;
-    return QLESS_OK;
-}
+// Workspace of qless_q_from_r: R^{-1} (n x n) and an int status word.
+static size_t q_from_r_work_bytes(int64_t n) { return align_up((size_t)(n * n) * sizeof(double), 256) + 256; }
 
 static int check_work(const void* work, size_t have, size_t need) {
     if (need == 0) return QLESS_OK;
@@ -172,6 +167,7 @@ size_t qless_workspace_bytes(int method, int64_t m, int64_t n) {
         case QLESS_METHOD_CHOLQR2:
         case QLESS_METHOD_SVQB:
         case QLESS_METHOD_SHIFTED_CHOLQR3: return gram_work_layout(make_gram_plan(m, n, d.num_cus), n, nullptr).bytes;
+        case QLESS_METHOD_Q_FROM_R: return q_from_r_work_bytes(n);
         default: return 0;
     }
 }
@@ -246,6 +242,47 @@ int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_
         e = launch_tsqr(Zt, n, n, n, Z_or_R, ldz, gw.tsqr_work, tp, stream);
     }
     if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int svqb_q(const double* X, int64_t m, int64_t n, int64_t ldx, double* Q, int64_t ldq, double* Z, int64_t ldz,
+           double* sigma, double trunc_tol, int32_t* info, void* work, size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, Z, ldz);
+    if (st != QLESS_OK) return st;
+    if ((m > 0 && Q == nullptr) || ldq < n) return QLESS_ERR_ARG;
+    if (!(trunc_tol > 0.0)) trunc_tol = (double)n * 2.220446049250313e-16;
+    const DeviceInfo& d = current_device_info();
+    GramPlan gp = make_gram_plan(m, n, d.num_cus);
+    GramWork gw = gram_work_layout(gp, n, work);
+    st = check_work(work, work_bytes, gw.bytes);
+    if (st != QLESS_OK) return st;
+    const int ni = (int)n;
+    double* U1 = gw.A1;
+    double* D1 = gw.A2;
+    double* Dq = gw.A4;
+    hipError_t e = launch_gram(X, m, n, ldx, nullptr, false, gw.Cpart, gw.C, gp, stream);
+    if (e == hipSuccess)
+        e = launch_svqb_eig(gw.C, ni, trunc_tol, 1, U1, gw.vec, D1, sigma, nullptr, 0, gw.iw, stream);
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, D1, false, gw.Cpart, gw.C, gp, stream);
+    if (e == hipSuccess)
+        e = launch_svqb_eig(gw.C, ni, trunc_tol, 0, U1, gw.vec, nullptr, nullptr, Z, ldz, gw.iw, stream, D1, Dq);
+    if (e == hipSuccess) e = launch_apply_right(X, m, n, ldx, Dq, false, Q, ldq, nullptr, stream);
+    if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int qless_q_from_r(const double* X, int64_t m, int64_t n, int64_t ldx, const double* R, int64_t ldr, double* Q,
+                   int64_t ldq, int32_t* info, void* work, size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, R, ldr);
+    if (st != QLESS_OK) return st;
+    if ((m > 0 && Q == nullptr) || ldq < n) return QLESS_ERR_ARG;
+    st = check_work(work, work_bytes, q_from_r_work_bytes(n));
+    if (st != QLESS_OK) return st;
+    double* Rinv = static_cast<double*>(work);
+    int* iw = reinterpret_cast<int*>(static_cast<char*>(work) + align_up((size_t)(n * n) * sizeof(double), 256));
+    hipError_t e = launch_trinv(R, ldr, (int)n, Rinv, iw, stream);
+    if (e == hipSuccess) e = launch_apply_right(X, m, n, ldx, Rinv, true, Q, ldq, iw, stream);
+    if (e == hipSuccess && info) e = launch_copy_int(iw, info, stream);
     return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 

@@ -372,6 +372,178 @@ int gram_npad(int64_t n) {
     return np;
 }
 
+// ------------------------------------------------------- explicit Q = X M
+//
+// Q = X M, streamed once over X (read 8mn bytes, write 8mn), for the explicit
+// Q that Sec. 1 says can be rebuilt from X and its Q-less R (M = R^{-1}), and
+// for the Q of SVQB's X = Q Z (M = D1 D2).  Same loads and products as the
+// Gram pass 2 above, but the rows of Y = X M are stored instead of being
+// multiplied into a Gram matrix.  A non-zero *fail (a singular R) makes every
+// row NaN instead.
+
+// n > 8, matrix cores: lane l's accumulator v of column block J holds
+// Y[r0 + 16u + 4v + l/16][16J + l%16]; the 16 lanes of a row write 128
+// contiguous bytes.
+template <int NB, int MK, bool GUARD>
+__device__ __forceinline__ void apply_stage(const GramStage<NB>& b, const double* __restrict__ Ms,
+                                            double* __restrict__ Q, int n, int64_t ldq, int64_t r0, int64_t r_end,
+                                            int lo, int hi) {
+    constexpr int NPAD = 16 * NB;
+    constexpr int U = gram_sub_blocks<NB>();
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        f64x4 y[NB];
+#pragma unroll
+        for (int J = 0; J < NB; ++J) y[J] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4 * NB; ++k)
+#pragma unroll
+            for (int J = 0; J < NB; ++J)
+                if (MK == 1 || k < 4 * (J + 1))
+                    y[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(b.v[u][k], Ms[(4 * k + hi) * NPAD + 16 * J + lo], y[J],
+                                                               0, 0, 0);
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + 16 * u + 4 * v + hi;
+                const int col = 16 * J + lo;
+                if (!GUARD || (row < r_end && col < n)) Q[row * ldq + col] = y[J][v];
+            }
+    }
+}
+
+template <int NB, int MK, bool GUARD>
+__device__ __forceinline__ void apply_range(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                            int64_t r_end, const double* __restrict__ Ms, double* __restrict__ Q,
+                                            int64_t ldq, int lo, int hi) {
+    constexpr int64_t STAGE = 16 * gram_sub_blocks<NB>();
+    const int64_t nfull = (r_end - r_begin) / STAGE;
+    if (nfull > 0) {
+        const int64_t last = r_begin + (nfull - 1) * STAGE;
+        GramStage<NB> ba, bb;
+        gram_load_stage<NB, true, GUARD>(ba, X, n, ldx, r_begin, r_end, lo, hi);
+        for (int64_t r0 = r_begin;;) {
+            gram_load_stage<NB, true, GUARD>(bb, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
+            apply_stage<NB, MK, GUARD>(ba, Ms, Q, n, ldq, r0, r_end, lo, hi);
+            r0 += STAGE;
+            if (r0 > last) break;
+            gram_load_stage<NB, true, GUARD>(ba, X, n, ldx, r0 + STAGE < last ? r0 + STAGE : last, r_end, lo, hi);
+            apply_stage<NB, MK, GUARD>(bb, Ms, Q, n, ldq, r0, r_end, lo, hi);
+            r0 += STAGE;
+            if (r0 > last) break;
+        }
+    }
+    const int64_t rt = r_begin + nfull * STAGE;
+    if (rt < r_end) {
+        GramStage<NB> bt;
+        gram_load_stage<NB, true, true>(bt, X, n, ldx, rt, r_end, lo, hi);
+        apply_stage<NB, MK, true>(bt, Ms, Q, n, ldq, rt, r_end, lo, hi);
+    }
+}
+
+// NaN rows [r_begin, r_end) of Q (the result of a failed call).
+__device__ __forceinline__ void fill_nan_rows(double* __restrict__ Q, int n, int64_t ldq, int64_t r_begin,
+                                              int64_t r_end, int lane) {
+    for (int64_t r = r_begin; r < r_end; ++r)
+        for (int c = lane; c < n; c += kWave) Q[r * ldq + c] = __builtin_nan("");
+}
+
+template <int NB, int MK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+apply_mfma_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                  int64_t nwaves, const double* __restrict__ M, double* __restrict__ Q, int64_t ldq,
+                  const int* __restrict__ fail) {
+    constexpr int NPAD = 16 * NB;
+    __shared__ double Ms[NPAD * NPAD];
+    for (int e = threadIdx.x; e < NPAD * NPAD; e += blockDim.x) {
+        const int k = e / NPAD, c = e % NPAD;
+        Ms[e] = (k < n && c < n) ? M[(int64_t)k * n + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nwaves) return;
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    if (fail != nullptr && *fail != 0) {
+        fill_nan_rows(Q, n, ldq, r_begin, r_end, lane);
+        return;
+    }
+    const int lo = lane & 15, hi = lane >> 4;
+    if (n == NPAD) apply_range<NB, MK, false>(X, n, ldx, r_begin, r_end, Ms, Q, ldq, lo, hi);
+    else apply_range<NB, MK, true>(X, n, ldx, r_begin, r_end, Ms, Q, ldq, lo, hi);
+}
+
+// n <= 8, row layout: each lane holds RPL full rows of a 64*RPL-row panel (the
+// TSQR panel loads), forms y = x M (M from LDS, broadcast reads) and writes
+// its rows of Q; lanes write consecutive rows.
+template <int NP, int RPL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+apply_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
+                  int64_t nwaves, const double* __restrict__ M, double* __restrict__ Q, int64_t ldq,
+                  const int* __restrict__ fail) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    __shared__ double Ms[NP * NP];
+    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
+        const int k = e / NP, c = e % NP;
+        Ms[e] = (k < n && c < n) ? M[(int64_t)k * n + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nwaves) return;
+    const int64_t r_begin = w * rows_per_wave;
+    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+    if (fail != nullptr && *fail != 0) {
+        fill_nan_rows(Q, n, ldq, r_begin, r_end, lane);
+        return;
+    }
+    const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
+    // 16-byte stores of column pairs when every row of Q starts 16-byte aligned
+    const bool vec_store = (n == NP) && (ldq % 2 == 0) && (reinterpret_cast<uintptr_t>(Q) % 16 == 0);
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        double x[RPL][NP];
+        const bool full = base + PANEL <= r_end;
+        if (fast && full) tsqr_detail::load_panel_1d_fast<NP, RPL>(x, X, ldx, base, lane);
+        else tsqr_detail::load_panel_1d_tail<NP, RPL>(x, X, n, ldx, base, r_end, lane);
+        double y[RPL][NP];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) y[i][c] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const double mkc = Ms[k * NP + c];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) y[i][c] = fma(x[i][k], mkc, y[i][c]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int64_t row = base + lane + kWave * i;
+            if (row < r_end) {
+                double* q = Q + row * ldq;
+                bool done = false;
+                if constexpr (NP % 2 == 0) {
+                    if (vec_store) {
+#pragma unroll
+                        for (int c = 0; c < NP; c += 2)
+                            *reinterpret_cast<f64x2*>(q + c) = f64x2{y[i][c], y[i][c + 1]};
+                        done = true;
+                    }
+                }
+                if (!done) {
+#pragma unroll
+                    for (int c = 0; c < NP; ++c)
+                        if (c < n) q[c] = y[i][c];
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus) {
@@ -416,6 +588,39 @@ hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)ceil_div(n * n, kSumEntries)), dim3(256), 0, s, Cpart, plan.k, ni,
                        C);
+    return hipGetLastError();
+}
+
+// Plan of the apply pass: the Gram pass's split of the rows over 8 wavefronts
+// per CU, whole slabs per wavefront.
+hipError_t launch_apply_right(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, bool m_upper,
+                              double* Q, int64_t ldq, const int* fail, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const GramPlan plan = make_gram_plan(m, n, current_device_info().num_cus);
+    const int ni = (int)n;
+    const int64_t rpw = plan.rows_per_wave, k = plan.k;
+    const unsigned blocks = (unsigned)ceil_div(k, 4);
+    switch (plan.npad) {
+#define QLESS_AROWS(NP)                                                                                   \
+    case NP:                                                                                              \
+        hipLaunchKernelGGL((apply_rows_kernel<NP, 32 / NP>), dim3(blocks), dim3(256), 0, s, X, m, ni, ldx, rpw, \
+                           k, M, Q, ldq, fail);                                                           \
+        break;
+#define QLESS_AMFMA(NB)                                                                                     \
+    case 16 * NB:                                                                                           \
+        if (m_upper)                                                                                        \
+            hipLaunchKernelGGL((apply_mfma_kernel<NB, 2>), dim3(blocks), dim3(256), 0, s, X, m, ni, ldx, rpw, k, M, Q, \
+                               ldq, fail);                                                                  \
+        else                                                                                                \
+            hipLaunchKernelGGL((apply_mfma_kernel<NB, 1>), dim3(blocks), dim3(256), 0, s, X, m, ni, ldx, rpw, k, M, Q, \
+                               ldq, fail);                                                                  \
+        break;
+        QLESS_AROWS(1) QLESS_AROWS(2) QLESS_AROWS(4) QLESS_AROWS(8)
+        QLESS_AMFMA(1) QLESS_AMFMA(2) QLESS_AMFMA(3) QLESS_AMFMA(4)
+#undef QLESS_AROWS
+#undef QLESS_AMFMA
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -212,7 +212,12 @@ struct TsqrPlan {
     size_t work_bytes = 0;     // total workspace
 };
 
-TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus);
+// tuned = false ignores the qless_tune_set overrides (the default instance).
+TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned = true);
+// The tree of a plan over k >= 2 stacked triangles in src (dst takes the
+// intermediate levels); writes R (ld ldr) with a non-negative diagonal.
+hipError_t launch_tsqr_tree(const TsqrPlan& plan, double* src, double* dst, int64_t k, int64_t n, double* R,
+                            int64_t ldr, hipStream_t stream);
 
 // Per-n launch-parameter overrides (0 = default); see qless_tune_set.
 int tsqr_tune_set(int64_t n, int waves_per_cu, int fan_in, int rows_per_lane);
@@ -258,8 +263,19 @@ hipError_t launch_trmm_out(const double* R2, const double* R1, int n, double* ou
 //   first pass (first != 0): D = U L^{-1/2} (truncated), U1 and lam1 kept,
 //   sigma (may be null) = sqrt(lam); second pass: Z = L2^{1/2} U2^T L1^{1/2} U1^T.
 // *ntrunc accumulates the number of truncated eigenvalues (first pass resets it).
+//   with Dq (second pass, D1 = the first pass's D): Dq = D1 U2 L2^{-1/2}, the
+//   right factor of the explicit Q = X Dq.
 hipError_t launch_svqb_eig(const double* C, int n, double trunc_tol, int first, double* U1, double* lam1,
-                           double* D, double* sigma, double* Z, int64_t ldz, int* ntrunc, hipStream_t stream);
+                           double* D, double* sigma, double* Z, int64_t ldz, int* ntrunc, hipStream_t stream,
+                           const double* D1 = nullptr, double* Dq = nullptr);
+// Rinv = R^{-1} for upper-triangular R (ld ldr); *info (may be null) = 0, or
+// the 1-based column of the first zero diagonal entry (Rinv is NaN then).
+hipError_t launch_trinv(const double* R, int64_t ldr, int n, double* Rinv, int* info, hipStream_t stream);
+// Q = X M (m x n, ld ldq) for an n x n M (ld n), streamed once over X; with
+// m_upper, M is upper triangular and its zero blocks are not multiplied.
+// A non-zero *fail (may be null) fills Q with NaN instead.
+hipError_t launch_apply_right(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, bool m_upper,
+                              double* Q, int64_t ldq, const int* fail, hipStream_t stream);
 // x = RA^{-1} z and |rho| from Rt = R([A b]) ((n+1) x (n+1), ld ldr).
 hipError_t launch_lstsq(const double* Rt, int n, int64_t ldr, double* x, double* resid, int* info,
                         hipStream_t stream);
@@ -297,6 +313,16 @@ void timing_end(int which, hipStream_t stream);
 enum { kTimeTsqrStage1 = 0, kTimeGram = 1, kTimeSlots = 2 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Host-side checks shared by the entry points taking one m x n matrix X and
+// an n x n result R (returns a qless_status).
+inline int check_matrix_args(const void* X, int64_t m, int64_t n, int64_t ldx, const void* R, int64_t ldr) {
+    if (n < 1 || m < 0) return QLESS_ERR_ARG;
+    if (n > QLESS_MAX_N) return QLESS_ERR_UNSUPPORTED;
+    if (R == nullptr || ldr < n) return QLESS_ERR_ARG;
+    if (m > 0 && (X == nullptr || ldx < n)) return QLESS_ERR_ARG;
+    return QLESS_OK;
+}
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace qless

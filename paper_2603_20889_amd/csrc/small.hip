@@ -91,7 +91,8 @@ trmm_out_kernel(const double* __restrict__ R2, const double* __restrict__ R1, in
 __global__ void __launch_bounds__(256)
 svqb_eig_kernel(const double* __restrict__ C, int n, double trunc_tol, int first, double* __restrict__ U1,
                 double* __restrict__ lam1, double* __restrict__ D, double* __restrict__ sigma,
-                double* __restrict__ Z, int64_t ldz, int* __restrict__ ntrunc) {
+                double* __restrict__ Z, int64_t ldz, int* __restrict__ ntrunc, const double* __restrict__ D1,
+                double* __restrict__ Dq) {
     __shared__ double A[64 * kLd];
     __shared__ double V[64 * kLd];
     __shared__ double cs_c[32], cs_s[32];
@@ -222,6 +223,58 @@ svqb_eig_kernel(const double* __restrict__ C, int n, double trunc_tol, int first
         const double l2 = lam[i];
         Z[(int64_t)i * ldz + c] = (l2 > 0.0 ? sqrt(l2) : 0.0) * s + 0.0;
     }
+    if (Dq == nullptr) return;
+    // Dq = D1 D2 with D2 = U2 L2^{-1/2} (truncated as in the first pass), so
+    // that Q = X Dq is the explicit Q of X = Q Z
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int k = e / n, t = e % n;
+        const bool keep = lam[t] > trunc_tol * lam[0] && lam[t] > 0.0;
+        A[k * kLd + t] = keep ? V[k * kLd + order[t]] / sqrt(lam[t]) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, c = e % n;
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s = fma(D1[i * n + k], A[k * kLd + c], s);
+        Dq[e] = s;
+    }
+}
+
+// Inverse of an upper-triangular R (ld ldr, any diagonal signs) into Rinv
+// (n x n, ld n, zeros below the diagonal): thread c owns column c of Rinv
+// and solves R t = e_c by back substitution.  A zero diagonal entry (R
+// singular) sets *info to its column (1-based) and fills Rinv with NaN.
+__global__ void __launch_bounds__(64)
+trinv_kernel(const double* __restrict__ R, int64_t ldr, int n, double* __restrict__ Rinv, int* __restrict__ info) {
+    __shared__ double A[64 * kLd];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int a = e / n, b = e % n;
+        A[a * kLd + b] = b >= a ? R[(int64_t)a * ldr + b] : 0.0;
+    }
+    if (tid == 0) {
+        int j = 0;
+        while (j < n && R[(int64_t)j * ldr + j] != 0.0) ++j;
+        bad = j < n ? j + 1 : 0;
+        if (info) *info = bad;
+    }
+    __syncthreads();
+    if (bad) {
+        for (int e = tid; e < n * n; e += blockDim.x) Rinv[e] = __builtin_nan("");
+        return;
+    }
+    if (tid < n) {
+        const int c = tid;
+        double t[64];
+        t[c] = 1.0 / A[c * kLd + c];
+        for (int r = c - 1; r >= 0; --r) {
+            double s = 0.0;
+            for (int k = r + 1; k <= c; ++k) s = fma(A[r * kLd + k], t[k], s);
+            t[r] = -s / A[r * kLd + r];
+        }
+        for (int r = 0; r < n; ++r) Rinv[r * n + c] = r <= c ? t[r] : 0.0;
+    }
 }
 
 // Back substitution RA x = z from Rt = [[RA, z], [0, rho]] (one thread).
@@ -259,9 +312,15 @@ hipError_t launch_trmm_out(const double* R2, const double* R1, int n, double* ou
 }
 
 hipError_t launch_svqb_eig(const double* C, int n, double trunc_tol, int first, double* U1, double* lam1,
-                           double* D, double* sigma, double* Z, int64_t ldz, int* ntrunc, hipStream_t s) {
+                           double* D, double* sigma, double* Z, int64_t ldz, int* ntrunc, hipStream_t s,
+                           const double* D1, double* Dq) {
     hipLaunchKernelGGL(svqb_eig_kernel, dim3(1), dim3(256), 0, s, C, n, trunc_tol, first, U1, lam1, D, sigma, Z,
-                       ldz, ntrunc);
+                       ldz, ntrunc, D1, Dq);
+    return hipGetLastError();
+}
+
+hipError_t launch_trinv(const double* R, int64_t ldr, int n, double* Rinv, int* info, hipStream_t s) {
+    hipLaunchKernelGGL(trinv_kernel, dim3(1), dim3(64), 0, s, R, ldr, n, Rinv, info);
     return hipGetLastError();
 }
 

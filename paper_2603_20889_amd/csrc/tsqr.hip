@@ -137,9 +137,9 @@ int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rpl) {
     return QLESS_OK;
 }
 
-TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus) {
+TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned) {
     TsqrPlan p;
-    const Tuning t = (n >= 1 && n <= QLESS_MAX_N) ? g_tuning[n] : Tuning{};
+    const Tuning t = (tuned && n >= 1 && n <= QLESS_MAX_N) ? g_tuning[n] : Tuning{};
     const Instance* in = find_instance(npad_for(n), t.rpl);
     p.npad = in->npad;
     p.rows_per_lane = in->rpl;
@@ -222,6 +222,13 @@ __global__ void copy_upper_kernel(const double* __restrict__ R, int64_t ldr, int
 }
 
 }  // namespace
+
+hipError_t launch_tsqr_tree(const TsqrPlan& plan, double* src, double* dst, int64_t k, int64_t n, double* R,
+                            int64_t ldr, hipStream_t stream) {
+    const Instance* in = find_instance(plan.npad, plan.rows_per_lane);
+    if (!in) return hipErrorInvalidValue;
+    return launch_tree(in, plan, src, dst, k, n, R, ldr, stream);
+}
 
 hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr,
                        void* work, const TsqrPlan& plan, hipStream_t stream) {

@@ -47,6 +47,7 @@ class Request:
     done_s: float = math.nan
     rows_done: int = 0
     x: object = None
+    R: object = None          # final R([A b]) on the device, when the executor keeps it
     resid: float = math.nan
     info: int = 0
     state: object = None      # executor-owned per-request state (data, running R)
@@ -71,7 +72,7 @@ class GpuExecutor:
     stream, and the device is waited for when a result is read."""
 
     def __init__(self, device, tile_bytes: int = 1 << 20, data_fn: Optional[Callable] = None,
-                 mode: str = "batched"):
+                 mode: str = "batched", keep_r: bool = False):
         import torch
 
         import paper_2603_20889_amd as q
@@ -86,6 +87,7 @@ class GpuExecutor:
         self._data = data_fn or (lambda r: workloads.ls_request_data(r.m, r.n, r.seed, device=device)[0])
         self.stream = torch.cuda.current_stream(device)
         self.steps = 0
+        self.keep_r = keep_r
         self._work = None
 
     def _workspace(self, nbytes: int):
@@ -128,6 +130,8 @@ class GpuExecutor:
         r.x = x.cpu().numpy()
         r.resid = float(res.item())
         r.info = int(info.item())
+        if self.keep_r:
+            r.R = r.state["R"]
         r.state = None
 
 

@@ -113,3 +113,30 @@ def test_update_argument_and_workspace_errors():
     assert need >= 2 * 8 * 8 * 8 * 8 > q.qless_workspace_bytes(q.QLESS_METHOD_TSQR, 0, 8)
     assert lib.qless_tsqr_r_update(NULL, 0, 8, 8, FAKE, 8, NULL, need, NULL) == q.QLESS_ERR_WORKSPACE
     assert lib.qless_tsqr_r_update(FAKE, 10_000, 8, 8, FAKE, 8, FAKE, need - 1, NULL) == q.QLESS_ERR_WORKSPACE
+
+
+def test_two_phase_argument_errors_on_host():
+    lib = q.load()
+    # p + n above the kernel limit, negative sizes, missing outputs
+    assert lib.qless_two_phase_r(FAKE, 40, 40, FAKE, 100, 30, 30, FAKE, 30, FAKE, 30, FAKE, 1 << 20, NULL) == \
+        q.QLESS_ERR_UNSUPPORTED
+    assert lib.qless_two_phase_r(FAKE, -1, 4, FAKE, 100, 3, 3, FAKE, 3, FAKE, 3, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_two_phase_r(FAKE, 4, 4, FAKE, 100, 3, 3, NULL, 3, FAKE, 3, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_two_phase_r(FAKE, 4, 3, FAKE, 100, 3, 3, FAKE, 3, FAKE, 3, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_two_phase_r(FAKE, 4, 4, FAKE, 100, 3, 3, FAKE, 3, NULL, 3, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    need = lib.qless_two_phase_workspace_bytes(10_000_000, 4, 3)
+    assert need > 0 and lib.qless_two_phase_workspace_bytes(100, 40, 30) == 0
+    assert lib.qless_two_phase_r(FAKE, 4, 4, FAKE, 10_000_000, 3, 3, FAKE, 3, FAKE, 3, FAKE, need - 1, NULL) == \
+        q.QLESS_ERR_WORKSPACE
+
+
+def test_q_from_r_argument_errors_on_host():
+    lib = q.load()
+    assert lib.qless_q_from_r(FAKE, 100, 4, 4, FAKE, 4, NULL, 4, NULL, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_q_from_r(FAKE, 100, 4, 4, FAKE, 4, FAKE, 3, NULL, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_q_from_r(FAKE, 100, 65, 65, FAKE, 65, FAKE, 65, NULL, FAKE, 1 << 20, NULL) == \
+        q.QLESS_ERR_UNSUPPORTED
+    need = q.qless_workspace_bytes(q.QLESS_METHOD_Q_FROM_R, 100, 4)
+    assert need > 0
+    assert lib.qless_q_from_r(FAKE, 100, 4, 4, FAKE, 4, FAKE, 4, NULL, NULL, need, NULL) == q.QLESS_ERR_WORKSPACE
+    assert lib.svqb_q(FAKE, 100, 4, 4, NULL, 4, FAKE, 4, NULL, 0.0, NULL, FAKE, 1 << 30, NULL) == q.QLESS_ERR_ARG

@@ -67,3 +67,15 @@ def test_committed_traffic_record_is_consistent():
     assert abs(rd + wr - d["traffic_bytes_per_launch"]) <= 1e-5 * (rd + wr)
     assert abs(c["fetch_factor"] - 1048576 / c["fetch_size_kib"]) < 1e-5
     assert d["traffic_bytes_per_launch"] >= d["algorithmic_bytes_per_launch"]
+
+
+def test_host_threads_follows_affinity_and_omp_cap(monkeypatch):
+    avail = len(os.sched_getaffinity(0))
+    monkeypatch.delenv("OMP_NUM_THREADS", raising=False)
+    assert bench.host_threads() == (avail, avail)
+    monkeypatch.setenv("OMP_NUM_THREADS", "1")
+    assert bench.host_threads() == (1, avail)
+    monkeypatch.setenv("OMP_NUM_THREADS", str(avail + 5))
+    assert bench.host_threads() == (avail, avail)
+    monkeypatch.setenv("OMP_NUM_THREADS", "junk")
+    assert bench.host_threads() == (avail, avail)

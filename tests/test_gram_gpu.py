@@ -176,3 +176,60 @@ def test_config2_full_size_gram_forms(gpu):
     assert int(info.item()) == 0 and int(info2.item()) == 0
     assert oracle.rel_err_r(R1.cpu().numpy(), R0) <= E_R
     assert oracle.rel_err_r(R2.cpu().numpy(), R0) <= E_R
+
+
+# Full-size code path of the Gram kernels.  The plan gives each of the
+# 8 * CUs wavefronts a contiguous range of rows, rounded to whole slabs; at
+# the sizes above every wavefront holds a single stage, so only the guarded
+# tail loader runs.  Here m is chosen per kernel width so that every
+# wavefront streams several full stages through the unguarded,
+# double-buffered loop (the path the benchmark sizes take), and the last
+# wavefront also ends in a partial stage.  Stage heights: 16 * (8, 4, 2, 1)
+# rows for 1..4 blocks of 16 columns; the row kernel for n <= 8 uses panels
+# of 64 * 64 / n rows (64 * 32 / n with the fused multiply).
+FULL_PATH = [
+    # (n, rows per wavefront): 16-column blocks NB = ceil(n / 16)
+    (16, 448), (13, 448),          # NB = 1: three 128-row stages + a 64-row tail
+    (32, 256), (30, 256),          # NB = 2: four 64-row stages
+    (48, 192), (47, 192),          # NB = 3: six 32-row stages
+    (64, 128), (61, 128),          # NB = 4: eight 16-row stages
+    (8, 2048), (3, 4096), (2, 4096), (1, 8192),   # row kernel: four full panels of pass 1
+]
+
+
+def full_path_matrix(gpu, n, rpw, seed):
+    cus = torch.cuda.get_device_properties(gpu).multi_processor_count
+    m = cus * 8 * rpw - 40
+    X, R0 = wl.known_r(m, n, wl.logspace_sigma(n, 3), seed=seed)
+    return X, R0, m
+
+
+def check_gram_r(X, R, Ro):
+    assert oracle.rel_err_r(R, Ro) <= E_R
+    assert oracle.row_scaled_err(R, Ro) <= 5e-12
+    assert oracle.gram_residual(X, R) <= E_G
+
+
+@pytest.mark.parametrize("n,rpw", FULL_PATH)
+def test_gram_forms_full_size_path(gpu, n, rpw):
+    X, R0, m = full_path_matrix(gpu, n, rpw, seed=31 * n + rpw)
+    print("case gram full path m=%d n=%d" % (m, n), flush=True)
+    Xd = dev_tensor(X, gpu)
+    Rc, ic = q.cholqr2_r(Xd)
+    Rs, ss, is_ = q.svqb(Xd, out=q.QLESS_SVQB_R)
+    R3, i3 = q.shifted_cholqr3_r(Xd)
+    torch.cuda.synchronize(gpu)
+    del Xd
+    assert int(ic.item()) == 0 and int(is_.item()) == 0 and int(i3.item()) == 0
+    Rh = oracle.householder_r(X)
+    Ro, info_o = oracle.cholqr2_r(X)
+    assert info_o == 0
+    check_gram_r(X, Rc.cpu().numpy(), Ro)
+    R3o, info3 = oracle.shifted_cholqr3_r(X)
+    assert info3 == 0
+    check_gram_r(X, R3.cpu().numpy(), R3o)
+    Zo, sig_o, Rso, nt = oracle.svqb2(X)
+    assert nt == 0
+    check_gram_r(X, Rs.cpu().numpy(), Rso)
+    for R in (Rc, Rs, R3):
+        assert oracle.rel_err_r(R.cpu().numpy(), Rh) <= E_R

@@ -236,3 +236,17 @@ def ls_request_data(m: int, n: int, seed: int, noise: float = 1e-6, device=None)
     e = torch.randn(m, dtype=torch.float64, device=device, generator=tg)
     Ab[:, n] = Ab[:, :n] @ x0 + noise * e
     return Ab, x0.cpu().numpy()
+
+
+def two_phase_data(m: int, p: int, n: int, k: float, seed: int):
+    """(Y, X, B0, R0) for the two-phase problem: [Y W] = H_1 ... H_{p+n} [I; 0]
+    with orthonormal columns (m x (p+n)), B0 iid N(0,1) (p x n), R0 upper
+    triangular with singular values 1 .. 10^-k, X = Y B0 + W R0 -- so that
+    Y^T X = B0 and R((I - Y Y^T) X) = R0."""
+    g = rng(seed)
+    U = orthonormal_columns(m, p + n, g)
+    Y, W = np.ascontiguousarray(U[:, :p]), U[:, p:]
+    B0 = g.standard_normal((p, n))
+    R0 = triangular_with_singular_values(logspace_sigma(n, k), g)
+    return Y, np.ascontiguousarray(Y @ B0 + W @ R0), B0, R0
+
