@@ -137,7 +137,7 @@ def main() -> int:
                     help="condition exponents k of the sweep (sigma down to 10^-k); timing runs at k = 4")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=300)
+    ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) for HBM-counter calibration")
     ap.add_argument("--tune", type=str, default="",
@@ -438,59 +438,64 @@ def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
     return res
 
 
-def bench_served(q, dev, log, count: int, distinct: int = 48):
+def bench_served(q, dev, log, count: int, loads=(0.5, 0.8, 0.95), pool_gb: float = 40.0, sample: int = 40):
     """Poisson least-squares requests [A b] (m log-uniform [1e4, 5e7], n in
-    3..47): continuous-batching server vs one request per launch, at 0.8x the
-    measured one-at-a-time capacity.  The first `distinct` requests' [A b]
-    (b = A x0 + 1e-6 noise) are built on the device before the clock starts
-    and later arrivals reuse them in turn, so latency is the solve, not the
-    synthetic data generation."""
+    3..47): the continuous-batching server (running TSQR state per request,
+    chunks of different requests on different streams, asynchronous
+    completion) vs one request per launch (FIFO), at 0.5x, 0.8x and 0.95x of
+    the measured one-at-a-time capacity.  Every request's [A b] is its own
+    window of a device-resident N(0,1) pool (a random offset per request), so
+    the data of all requests differ and none is generated inside the timed
+    serving loop.  Accuracy: the served R([A b]) of a sample of requests
+    against the same request solved alone."""
+    import numpy as np
     import torch
     import workloads as wl
     from paper_2603_20889_amd.server import FifoServer, GpuExecutor, LstsqServer, make_requests
 
-    def cycle(reqs):
-        for i, r in enumerate(reqs):
-            if i >= distinct:
-                src = reqs[i % distinct]
-                r.m, r.n, r.seed = src.m, src.n, src.seed
-        return reqs
-
-    reqs = cycle(make_requests(count, rate_per_s=1.0, seed=5))
-    pool = {}
-    for r in reqs[:distinct]:
-        pool[r.seed] = wl.ls_request_data(r.m, r.n, r.seed, device=dev)[0]
+    pool_len = int(pool_gb * 1e9 / 8)
+    pool = wl.gaussian_torch(pool_len, 1, seed=55, device=dev).view(-1)
+    shapes = [(r.m, r.n) for r in make_requests(count, rate_per_s=1.0, seed=5)]
+    g = wl.rng(56)
+    offs = [int(g.integers(0, pool_len - m * (n + 1) + 1)) for m, n in shapes]
+    data_fn = lambda r: pool[offs[r.id]:offs[r.id] + r.m * (r.n + 1)].view(r.m, r.n + 1)
+    total_gb = sum(8 * m * (n + 1) for m, n in shapes) / 1e9
+    log("served: %d requests, %.1f GB of [A b] in all, windows of a %.0f GB device pool" % (count, total_gb, pool_gb))
+    reqs_at = lambda rate: make_requests(count, rate_per_s=rate, seed=5)
+    warm = reqs_at(1e9)[:8]
+    FifoServer(GpuExecutor(dev, data_fn=data_fn)).run(warm, realtime=False)
     torch.cuda.synchronize()
-    data_fn = lambda r: pool[r.seed]
-    total_gb = sum(8 * r.m * (r.n + 1) for r in reqs) / 1e9
-    log("served: %d requests (%d distinct, %.1f GB resident), %.1f GB in total" %
-        (count, distinct, sum(v.numel() * 8 for v in pool.values()) / 1e9, total_gb))
-    # (the same count keeps the same shapes: the rate only scales the arrival gaps)
-    probe = cycle(make_requests(count, rate_per_s=1e9, seed=5))[:4]
-    FifoServer(GpuExecutor(dev, data_fn=data_fn)).run(probe, realtime=False)   # warm-up
-    torch.cuda.synchronize()
-    probe = cycle(make_requests(count, rate_per_s=1e9, seed=5))[:distinct]
+    probe = reqs_at(1e9)[:200]
     t0 = time.perf_counter()
     FifoServer(GpuExecutor(dev, data_fn=data_fn)).run(probe, realtime=False)
     torch.cuda.synchronize()
     capacity = len(probe) / (time.perf_counter() - t0)
-    rate = 0.8 * capacity
-    log("served: one-at-a-time capacity %.1f req/s, offered %.1f req/s" % (capacity, rate))
+    log("served: one-at-a-time capacity %.1f req/s" % capacity)
     fmt = lambda st: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
-    res = {"requests": count, "distinct_requests": distinct, "total_GB": round(total_gb, 1),
-           "offered_rate_per_s": round(rate, 1), "capacity_one_at_a_time_per_s": round(capacity, 1)}
+    res = {"requests": count, "distinct_requests": count, "total_GB": round(total_gb, 1),
+           "capacity_one_at_a_time_per_s": round(capacity, 1), "loads": []}
     bad = 0
-    for mode in ("update", "batched"):
-        reqs = cycle(make_requests(count, rate_per_s=rate, seed=5))
-        srv = LstsqServer(GpuExecutor(dev, data_fn=data_fn, mode=mode), hbm_budget_bytes=96 << 30,
-                          step_bytes=2 << 30, max_active=64)
-        res["server_" + mode] = fmt(srv.run(reqs, realtime=True))
+    for load in loads:
+        rate = load * capacity
+        reqs = reqs_at(rate)
+        srv = LstsqServer(GpuExecutor(dev, data_fn=data_fn, mode="state", keep_r=True),
+                          hbm_budget_bytes=96 << 30, step_bytes=4 << 30, max_active=64)
+        st_srv = fmt(srv.run(reqs, realtime=True))
         bad += sum(1 for r in reqs if r.info != 0)
-        log("served: server (%s steps) %s" % (mode, json.dumps(res["server_" + mode])))
-    reqs2 = cycle(make_requests(count, rate_per_s=rate, seed=5))
-    res["fifo_one_per_launch"] = fmt(FifoServer(GpuExecutor(dev, data_fn=data_fn)).run(reqs2, realtime=True))
+        st_fifo = fmt(FifoServer(GpuExecutor(dev, data_fn=data_fn)).run(reqs_at(rate), realtime=True))
+        # the served R of a sample against the same requests alone
+        ids = sorted(set(int(i) for i in wl.rng(57).integers(0, count, sample)))
+        err = 0.0
+        for i in ids:
+            r = reqs[i]
+            Ra = q.qless_tsqr_r(data_fn(r))
+            err = max(err, float(torch.linalg.norm(r.R - Ra) / torch.linalg.norm(Ra)))
+        rec = {"load": load, "offered_rate_per_s": round(rate, 1), "server": st_srv, "fifo_one_per_launch": st_fifo,
+               "sampled_requests": len(ids), "max_e_R_served_vs_alone": err}
+        res["loads"].append(rec)
+        log("served: %s" % json.dumps(rec))
+        del reqs, srv
     res["failed"] = bad
-    log("served: %s" % json.dumps(res))
     del pool
     torch.cuda.empty_cache()
     return res

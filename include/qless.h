@@ -58,7 +58,9 @@ typedef enum {
     QLESS_METHOD_SVQB = 2,       /* svqb */
     QLESS_METHOD_TSQR_UPDATE = 3, /* qless_tsqr_r_update */
     QLESS_METHOD_SHIFTED_CHOLQR3 = 4, /* shifted_cholqr3_r */
-    QLESS_METHOD_Q_FROM_R = 5     /* qless_q_from_r */
+    QLESS_METHOD_Q_FROM_R = 5,    /* qless_q_from_r */
+    QLESS_METHOD_GRAM = 6,        /* qless_gram */
+    QLESS_METHOD_CHOLQR2_DD = 7   /* cholqr2_dd_r */
 } qless_method;
 
 typedef enum {
@@ -121,6 +123,34 @@ int qless_tsqr_r_update(const double *X, int64_t m, int64_t n, int64_t ldx,
 int cholqr2_r(const double *X, int64_t m, int64_t n, int64_t ldx,
               double *R, int64_t ldr, int32_t *info, void *work,
               size_t work_bytes, hipStream_t stream);
+
+/*
+ * qless_gram -- the Gram matrix C = X^T X (tsmttsm, Alg. 1 step 1) on its
+ * own.  C_lo == NULL: FP64, as the first pass of cholqr2_r (matrix cores
+ * for n > 8).  C_lo != NULL: accumulated in twice the working precision
+ * (Dot2: error-free products and sums, the errors collected in a second
+ * word), C = C_hi + C_lo with each entry about as accurate as a 106-bit sum
+ * rounded once -- the higher-precision Gramian of the robust Gram variants
+ * (Sec. 2).  C and C_lo: device, n x n, ldc >= n (both triangles written).
+ * Workspace from qless_workspace_bytes(QLESS_METHOD_GRAM, m, n).
+ */
+int qless_gram(const double *X, int64_t m, int64_t n, int64_t ldx, double *C, int64_t ldc,
+               double *C_lo, void *work, size_t work_bytes, hipStream_t stream);
+
+/*
+ * cholqr2_dd_r -- Cholesky-QR2 with its first Gram matrix accumulated and
+ * factored in twice the working precision (the higher-precision Gramian
+ * that Sec. 2 cites, after Yamazaki et al. 2015): C1 = X^T X in
+ * double-double, R1 = chol(C1) and R1^{-1} in double-double, M = R1^{-1}
+ * rounded; then the plain second pass C2 = (X M)^T (X M), R2 = chol(C2) and
+ * R = R2 R1 (R1 in double-double).  Two passes over X like cholqr2_r, the
+ * first one FP64-compute bound; completes with a backward-stable R for
+ * kappa(X) up to about u^{-1}, where cholqr2_r breaks down at about
+ * u^{-1/2}.  Arguments, errors and info as for cholqr2_r (workspace
+ * QLESS_METHOD_CHOLQR2_DD).
+ */
+int cholqr2_dd_r(const double *X, int64_t m, int64_t n, int64_t ldx, double *R, int64_t ldr,
+                 int32_t *info, void *work, size_t work_bytes, hipStream_t stream);
 
 /*
  * shifted_cholqr3_r -- Q-less shifted Cholesky-QR3, the robust Gram variant
@@ -286,6 +316,63 @@ int qless_batch_plan_upload(const qless_batch_plan *plan, void *work, size_t wor
  * memset and keeps no state between calls, so the sequence can be captured
  * in a hipGraph and replayed.  Calls sharing a workspace must not overlap. */
 int qless_tsqr_r_batched(const qless_batch_plan *plan, void *work, size_t work_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------- more than 64 columns */
+
+/*
+ * qless_wide_r -- R (and the explicit Q) of an m x n X with n beyond one
+ * TSQR panel: block classical Gram-Schmidt with reorthogonalisation (BCGS2)
+ * over column panels of `panel` (<= QLESS_MAX_N) columns, the variant that
+ * stores Q which Sec. 4.6 names for more than 64 columns.  Each panel is
+ * orthogonalised twice against the Q of the earlier ones (library GEMMs),
+ * factored by the Q-less TSQR (R_jj, diagonal >= 0) and its Q rebuilt by
+ * the streaming Q = V R_jj^{-1} pass; R's block above R_jj is the sum of
+ * the two projections.  Needs m >= n and, for an accurate R, kappa(X) well
+ * below u^{-1/2} (BCGS2's range).
+ *
+ * X: device, m x n row-major, ldx >= n.  R: device, n x n, ldr >= n, zeros
+ * below the diagonal.  Q: device, m x n, ldq >= n (written: orthonormal
+ * columns, X = Q R).  info (device int32, may be NULL): 0, or the first
+ * column j (1-based) whose R_jj is zero -- Q is then NaN from that panel on.
+ * Workspace of qless_wide_workspace_bytes(m, n, panel) bytes.  Uses a
+ * rocBLAS handle per device, created on the first call (this entry point
+ * allocates on its first call on a device).
+ */
+size_t qless_wide_workspace_bytes(int64_t m, int64_t n, int64_t panel);
+int qless_wide_r(const double *X, int64_t m, int64_t n, int64_t ldx, double *R, int64_t ldr, double *Q,
+                 int64_t ldq, int64_t panel, int32_t *info, void *work, size_t work_bytes,
+                 hipStream_t stream);
+
+/* -------------------------------------------------- running factorisation */
+
+/*
+ * Running Q-less TSQR with the partial tree state on the device: the rows of
+ * one matrix arrive in chunks (any sizes, any number), each chunk is folded
+ * into a device state by one stage-1 launch, and a finishing call runs the
+ * stacked-R tree once (Alg. 2 with its first stage spread over several
+ * calls; the R of all rows seen, Sec. 1).  m_total is the planned total row
+ * count; it sizes the state and fixes the stage-1 split (one triangle per
+ * stage-1 workgroup of the qless_tsqr_r plan for m_total rows, without tuning
+ * overrides) and must be the same in every call on one state.  Folding
+ * chunks this way costs one launch per chunk and one tree in all, and gives
+ * R([X_1; X_2; ...]) for any chunking.
+ *
+ * state: device, qless_tsqr_state_bytes(m_total, n) bytes (0 for invalid
+ * sizes), 256-byte aligned, owned by the caller; it holds n x n triangles
+ * between the calls.  qless_tsqr_state_init clears it (a fill kernel, no
+ * memset, so the sequence can be captured).  qless_tsqr_state_fold folds X
+ * (m x n row-major, ldx >= n; m may be 0).  qless_tsqr_state_finish writes R
+ * (n x n, ldr >= n, diagonal >= 0) and consumes the state (init it again
+ * before reuse).  Calls on one state must be ordered on one stream (or by
+ * events).  Errors as for qless_tsqr_r; a state smaller than required is
+ * QLESS_ERR_WORKSPACE.
+ */
+size_t qless_tsqr_state_bytes(int64_t m_total, int64_t n);
+int qless_tsqr_state_init(void *state, size_t state_bytes, int64_t m_total, int64_t n, hipStream_t stream);
+int qless_tsqr_state_fold(const double *X, int64_t m, int64_t ldx, void *state, size_t state_bytes,
+                          int64_t m_total, int64_t n, hipStream_t stream);
+int qless_tsqr_state_finish(void *state, size_t state_bytes, int64_t m_total, int64_t n, double *R,
+                            int64_t ldr, hipStream_t stream);
 
 /* ---------------------------------------------------------- timing hooks */
 

@@ -229,18 +229,29 @@ def rel_err_r(R, R_ref) -> float:
     return float(d / nr) if nr > 0 else float(d)
 
 
-def row_scaled_err(R, R_ref) -> float:
-    """max over i, j of |R - R_ref|_ij / |R_ref|_ii: each row's error against
-    that row's own scale, so a wrong small trailing row is seen even where
-    the normwise e_R is dominated by the large leading rows.  Rows of R_ref
-    with a zero diagonal are left out (rank-deficient inputs)."""
+def row_scaled_err(R, R_ref, floor: float = 0.0) -> float:
+    """max over i, j of |R - R_ref|_ij / max(|R_ref|_ii, floor): each row's
+    error against that row's own scale, so a wrong small trailing row is seen
+    even where the normwise e_R is dominated by the large leading rows.  The
+    floor bounds the scale from below where a row is small only because the
+    input is ill-conditioned relative to its largest column (a backward
+    stable R has errors of about u times the largest column norm in every
+    row); with floor = 1e-4 * max_j ||x_j||, rows are judged as if kappa were
+    at most 1e4.  Rows whose scale is zero are left out (rank-deficient
+    inputs)."""
     R = np.asarray(R, dtype=np.float64)
     R_ref = np.asarray(R_ref, dtype=np.float64)
-    d = np.abs(np.diag(R_ref))
+    d = np.maximum(np.abs(np.diag(R_ref)), float(floor))
     ok = d > 0
     if not ok.any():
         return 0.0
     return float(np.max(np.abs(R - R_ref)[ok] / d[ok, None]))
+
+
+def col_norm_max(X) -> float:
+    """Largest column 2-norm of X (the scale of the backward error of R)."""
+    X = np.asarray(X, dtype=np.float64)
+    return float(np.sqrt(np.max(np.einsum("ij,ij->j", X, X)))) if X.size else 0.0
 
 
 def gram_residual(X, R, G=None) -> float:

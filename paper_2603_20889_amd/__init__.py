@@ -29,6 +29,8 @@ QLESS_METHOD_CHOLQR2 = 1
 QLESS_METHOD_SVQB = 2
 QLESS_METHOD_SHIFTED_CHOLQR3 = 4
 QLESS_METHOD_Q_FROM_R = 5
+QLESS_METHOD_GRAM = 6
+QLESS_METHOD_CHOLQR2_DD = 7
 
 QLESS_SVQB_R = 0
 QLESS_SVQB_QZ = 1
@@ -41,7 +43,9 @@ EXPORTED = (
     "qless_timing_read", "qless_batch_plan_create", "qless_batch_plan_destroy",
     "qless_batch_plan_workspace_bytes", "qless_batch_plan_tiles", "qless_batch_plan_upload",
     "qless_tsqr_r_batched", "qless_tune_set", "qless_tune_get", "qless_q_from_r", "svqb_q",
-    "qless_two_phase_r", "qless_two_phase_workspace_bytes",
+    "qless_two_phase_r", "qless_two_phase_workspace_bytes", "qless_tsqr_state_bytes", "qless_tsqr_state_init",
+    "qless_tsqr_state_fold", "qless_tsqr_state_finish", "qless_wide_r", "qless_wide_workspace_bytes",
+    "qless_gram", "cholqr2_dd_r",
 )
 
 
@@ -95,6 +99,22 @@ def load() -> ctypes.CDLL:
     lib.qless_two_phase_workspace_bytes.restype = sz
     lib.qless_two_phase_r.argtypes = [vp, i64, i64, vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp]
     lib.qless_two_phase_r.restype = ctypes.c_int
+    lib.qless_tsqr_state_bytes.argtypes = [i64, i64]
+    lib.qless_tsqr_state_bytes.restype = sz
+    lib.qless_tsqr_state_init.argtypes = [vp, sz, i64, i64, vp]
+    lib.qless_tsqr_state_init.restype = ctypes.c_int
+    lib.qless_tsqr_state_fold.argtypes = [vp, i64, i64, vp, sz, i64, i64, vp]
+    lib.qless_tsqr_state_fold.restype = ctypes.c_int
+    lib.qless_tsqr_state_finish.argtypes = [vp, sz, i64, i64, vp, i64, vp]
+    lib.qless_tsqr_state_finish.restype = ctypes.c_int
+    lib.qless_wide_workspace_bytes.argtypes = [i64, i64, i64]
+    lib.qless_wide_workspace_bytes.restype = sz
+    lib.qless_wide_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, i64, vp, vp, sz, vp]
+    lib.qless_wide_r.restype = ctypes.c_int
+    lib.qless_gram.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
+    lib.qless_gram.restype = ctypes.c_int
+    lib.cholqr2_dd_r.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]
+    lib.cholqr2_dd_r.restype = ctypes.c_int
     lib.qless_lstsq_finish.argtypes = [vp, i64, i64, vp, vp, vp, vp]
     lib.qless_lstsq_finish.restype = ctypes.c_int
     lib.qless_batch_plan_create.argtypes = [ctypes.POINTER(qless_matrix_desc), i32, i64, i32,
@@ -271,6 +291,63 @@ def cholqr2_r(X, R=None, info=None, work=None):
     return R, info
 
 
+def qless_gram(X, double_double: bool = False, C=None, C_lo=None, work=None):
+    """C = X^T X on the device (tsmttsm); with double_double, accumulated in
+    twice the working precision: returns (C_hi, C_lo), else (C, None)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if C is None:
+            C = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(C, n, n, dev, "C")
+        if double_double:
+            if C_lo is None:
+                C_lo = torch.empty((n, n), dtype=torch.float64, device=dev)
+            else:
+                _out(C_lo, n, n, dev, "C_lo")
+                if C_lo.stride(0) != C.stride(0):
+                    raise ValueError("C and C_lo must have the same row stride")
+        else:
+            C_lo = None
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_GRAM, m, n, dev)
+        else:
+            wb = _work_arg(work, dev)
+        st = load().qless_gram(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx, ctypes.c_void_p(C.data_ptr()),
+                               C.stride(0), ctypes.c_void_p(C_lo.data_ptr() if C_lo is not None else 0),
+                               ctypes.c_void_p(work.data_ptr()), wb, _stream(dev))
+    _check(st, "qless_gram")
+    return C, C_lo
+
+
+def cholqr2_dd_r(X, R=None, info=None, work=None):
+    """Cholesky-QR2 with the first Gram matrix and Cholesky in
+    double-double.  Returns (R, info)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(R, n, n, dev, "R")
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
+        if work is None:
+            work, wb = _workspace(QLESS_METHOD_CHOLQR2_DD, m, n, dev)
+        else:
+            wb = _work_arg(work, dev)
+        st = load().cholqr2_dd_r(ctypes.c_void_p(X.data_ptr() if m else 0), m, n, ldx,
+                                 ctypes.c_void_p(R.data_ptr()), R.stride(0), ctypes.c_void_p(info.data_ptr()),
+                                 ctypes.c_void_p(work.data_ptr()), wb, _stream(dev))
+    _check(st, "cholqr2_dd_r")
+    return R, info
+
+
 def shifted_cholqr3_r(X, R=None, info=None, work=None):
     """Q-less shifted CholQR3.  Returns (R, info) with info a 1-element int32
     device tensor (0 ok; j, n+j or 2n+j on Cholesky breakdown)."""
@@ -428,6 +505,38 @@ def qless_two_phase_r(Y, X, B=None, R=None, work=None):
     return B, R
 
 
+def qless_wide_r(X, panel: int = 64, R=None, Q=None, info=None, work=None):
+    """R and the explicit Q of X for any n (m >= n), by BCGS2 over column
+    panels of the Q-less TSQR (for n beyond 64).  Returns (R, Q, info)."""
+    import torch
+    X, m, n, ldx = _matrix(X)
+    dev = X.device
+    with torch.cuda.device(dev):
+        if R is None:
+            R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        else:
+            _out(R, n, n, dev, "R")
+        if Q is None:
+            Q = torch.empty((m, n), dtype=torch.float64, device=dev)
+        else:
+            _out(Q, m, n, dev, "Q")
+        if info is None:
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            _out(info, 0, 1, dev, "info", torch.int32)
+        nbytes = int(load().qless_wide_workspace_bytes(m, n, int(panel)))
+        if work is None:
+            work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+            wb = work.numel()
+        else:
+            wb = _work_arg(work, dev)
+        st = load().qless_wide_r(ctypes.c_void_p(X.data_ptr()), m, n, ldx, ctypes.c_void_p(R.data_ptr()), R.stride(0),
+                                 ctypes.c_void_p(Q.data_ptr()), Q.stride(0) if m > 1 else n, int(panel),
+                                 ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(work.data_ptr()), wb, _stream(dev))
+    _check(st, "qless_wide_r")
+    return R, Q, info
+
+
 def qless_lstsq_finish(Rt, x=None, resid=None, info=None):
     """x and |rho| from R([A b]) on the device (back substitution)."""
     import torch
@@ -454,6 +563,53 @@ def qless_lstsq_finish(Rt, x=None, resid=None, info=None):
                                        _stream(dev))
     _check(st, "qless_lstsq_finish")
     return x, resid, info
+
+
+# ------------------------------------------------------ running factorisation
+
+class TsqrState:
+    """Running Q-less TSQR of an m_total x n matrix whose rows arrive in
+    chunks: the stage-1 triangles stay on the device between ``fold`` calls
+    and ``finish`` runs the tree once (qless_tsqr_state_*).  Every call is
+    enqueued on ``stream`` (default: the current stream at construction)."""
+
+    def __init__(self, m_total: int, n: int, device, stream=None):
+        import torch
+        self.m_total, self.n, self.device = int(m_total), int(n), torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = int(load().qless_tsqr_state_bytes(self.m_total, self.n))
+        if self.nbytes == 0:
+            raise ValueError("invalid running-state sizes m_total=%d n=%d" % (m_total, n))
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.init()
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def init(self):
+        _check(load().qless_tsqr_state_init(ctypes.c_void_p(self.buf.data_ptr()), self.nbytes, self.m_total,
+                                            self.n, self._s()), "qless_tsqr_state_init")
+
+    def fold(self, X):
+        X, m, n, ldx = _matrix(X)
+        if n != self.n or X.device != self.device:
+            raise ValueError("chunk must have %d columns and live on %s" % (self.n, self.device))
+        _check(load().qless_tsqr_state_fold(ctypes.c_void_p(X.data_ptr() if m else 0), m, ldx,
+                                            ctypes.c_void_p(self.buf.data_ptr()), self.nbytes, self.m_total,
+                                            self.n, self._s()), "qless_tsqr_state_fold")
+
+    def finish(self, R=None):
+        import torch
+        if R is None:
+            with torch.cuda.stream(self.stream):
+                R = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        else:
+            _out(R, self.n, self.n, self.device, "R")
+        _check(load().qless_tsqr_state_finish(ctypes.c_void_p(self.buf.data_ptr()), self.nbytes, self.m_total,
+                                              self.n, ctypes.c_void_p(R.data_ptr()), R.stride(0), self._s()),
+               "qless_tsqr_state_finish")
+        return R
 
 
 # ----------------------------------------------------------------- batched

@@ -1,6 +1,7 @@
 // C-ABI of libqless: argument validation, workspace sizing and dispatch.
 // Every entry point validates on the host before any HIP call that could
 // launch work, so argument errors are testable without a GPU.
+#include <algorithm>
 #include <mutex>
 #include <string.h>
 #include <vector>
@@ -148,6 +149,54 @@ const char* qless_status_string(int status) {
 
 const char* qless_version(void) { return "qless 0.1 gfx950"; }
 
+// Workspace of qless_gram: the partials of either Gram kernel and C.
+static size_t gram_only_work_bytes(int64_t m, int64_t n) {
+    const int cus = current_device_info().num_cus;
+    const size_t plain = make_gram_plan(m, n, cus).part_bytes;
+    const size_t dd = make_gram_dd_plan(m, n, cus).part_bytes;
+    return std::max(plain, dd) + align_up((size_t)(n * n) * sizeof(double), 256);
+}
+
+// Workspace of cholqr2_dd_r: the double-double Gram partials, C (hi, lo),
+// R1 (hi, lo), M = R1^{-1}, the plain Gram pass (partials, C2), R2, R2^{-1}
+// and the status word.
+struct DdWork {
+    GramDdPlan dp;
+    GramPlan gp;
+    double *part = nullptr, *Chi = nullptr, *Clo = nullptr, *R1h = nullptr, *R1l = nullptr, *M = nullptr;
+    double *gpart = nullptr, *C2 = nullptr, *R2 = nullptr, *R2i = nullptr;
+    int* iw = nullptr;
+    size_t bytes = 0;
+};
+
+static DdWork cholqr2_dd_layout(int64_t m, int64_t n, void* base) {
+    DdWork w;
+    const int cus = current_device_info().num_cus;
+    w.dp = make_gram_dd_plan(m, n, cus);
+    w.gp = make_gram_plan(m, n, cus);
+    char* b = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t nb) -> char* {
+        char* p = b ? b + off : nullptr;
+        off += align_up(nb, 256);
+        return p;
+    };
+    const size_t sq = (size_t)(n * n) * sizeof(double);
+    w.part = reinterpret_cast<double*>(take(w.dp.part_bytes));
+    w.Chi = reinterpret_cast<double*>(take(sq));
+    w.Clo = reinterpret_cast<double*>(take(sq));
+    w.R1h = reinterpret_cast<double*>(take(sq));
+    w.R1l = reinterpret_cast<double*>(take(sq));
+    w.M = reinterpret_cast<double*>(take(sq));
+    w.gpart = reinterpret_cast<double*>(take(w.gp.part_bytes));
+    w.C2 = reinterpret_cast<double*>(take(sq));
+    w.R2 = reinterpret_cast<double*>(take(sq));
+    w.R2i = reinterpret_cast<double*>(take(sq));
+    w.iw = reinterpret_cast<int*>(take(sizeof(int)));
+    w.bytes = off;
+    return w;
+}
+
 // Workspace of qless_q_from_r: R^{-1} (n x n) and an int status word.
 static size_t q_from_r_work_bytes(int64_t n) { return align_up((size_t)(n * n) * sizeof(double), 256) + 256; }
 
@@ -168,6 +217,8 @@ size_t qless_workspace_bytes(int method, int64_t m, int64_t n) {
         case QLESS_METHOD_SVQB:
         case QLESS_METHOD_SHIFTED_CHOLQR3: return gram_work_layout(make_gram_plan(m, n, d.num_cus), n, nullptr).bytes;
         case QLESS_METHOD_Q_FROM_R: return q_from_r_work_bytes(n);
+        case QLESS_METHOD_GRAM: return gram_only_work_bytes(m, n);
+        case QLESS_METHOD_CHOLQR2_DD: return cholqr2_dd_layout(m, n, nullptr).bytes;
         default: return 0;
     }
 }
@@ -242,6 +293,45 @@ int svqb(const double* X, int64_t m, int64_t n, int64_t ldx, int out, double* Z_
         e = launch_tsqr(Zt, n, n, n, Z_or_R, ldz, gw.tsqr_work, tp, stream);
     }
     if (e == hipSuccess && info) e = launch_copy_int(gw.iw, info, stream);
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int qless_gram(const double* X, int64_t m, int64_t n, int64_t ldx, double* C, int64_t ldc, double* C_lo, void* work,
+               size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, C, ldc);
+    if (st != QLESS_OK) return st;
+    st = check_work(work, work_bytes, gram_only_work_bytes(m, n));
+    if (st != QLESS_OK) return st;
+    const int cus = current_device_info().num_cus;
+    hipError_t e;
+    if (C_lo != nullptr) {
+        e = launch_gram_dd(X, m, n, ldx, static_cast<double*>(work), C, C_lo, ldc, make_gram_dd_plan(m, n, cus), stream);
+    } else {
+        const GramPlan gp = make_gram_plan(m, n, cus);
+        double* Cw = reinterpret_cast<double*>(static_cast<char*>(work) + gram_only_work_bytes(m, n) -
+                                               align_up((size_t)(n * n) * sizeof(double), 256));
+        e = launch_gram(X, m, n, ldx, nullptr, false, static_cast<double*>(work), Cw, gp, stream);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(C, (size_t)ldc * sizeof(double), Cw, (size_t)n * sizeof(double),
+                                 (size_t)n * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, stream);
+    }
+    return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
+}
+
+int cholqr2_dd_r(const double* X, int64_t m, int64_t n, int64_t ldx, double* R, int64_t ldr, int32_t* info, void* work,
+                 size_t work_bytes, hipStream_t stream) {
+    int st = check_matrix_args(X, m, n, ldx, R, ldr);
+    if (st != QLESS_OK) return st;
+    const DdWork w = cholqr2_dd_layout(m, n, work);
+    st = check_work(work, work_bytes, w.bytes);
+    if (st != QLESS_OK) return st;
+    const int ni = (int)n;
+    hipError_t e = launch_gram_dd(X, m, n, ldx, w.part, w.Chi, w.Clo, n, w.dp, stream);        // C1 in dd
+    if (e == hipSuccess) e = launch_chol_dd(w.Chi, w.Clo, ni, w.R1h, w.R1l, w.M, w.iw, stream);   // R1, R1^{-1}
+    if (e == hipSuccess) e = launch_gram(X, m, n, ldx, w.M, true, w.gpart, w.C2, w.gp, stream);   // (X/R1)^T (X/R1)
+    if (e == hipSuccess) e = launch_chol_inv(w.C2, ni, w.R2, w.R2i, w.iw, ni, stream);            // R2
+    if (e == hipSuccess) e = launch_trmm_dd(w.R2, w.R1h, w.R1l, ni, R, ldr, w.iw, stream);        // R = R2 R1
+    if (e == hipSuccess && info) e = launch_copy_int(w.iw, info, stream);
     return e == hipSuccess ? QLESS_OK : QLESS_ERR_HIP;
 }
 

@@ -374,7 +374,8 @@ int gram_npad(int64_t n) {
 
 // ------------------------------------------------------- explicit Q = X M
 //
-// Q = X M, streamed once over X (read 8mn bytes, write 8mn), for the explicit
+// Q = X M, streamed once over X (read 8mn bytes, write 8mn with nontemporal
+// stores: Q is not read back by this call), for the explicit
 // Q that Sec. 1 says can be rebuilt from X and its Q-less R (M = R^{-1}), and
 // for the Q of SVQB's X = Q Z (M = D1 D2).  Same loads and products as the
 // Gram pass 2 above, but the rows of Y = X M are stored instead of being
@@ -409,7 +410,7 @@ __device__ __forceinline__ void apply_stage(const GramStage<NB>& b, const double
             for (int v = 0; v < 4; ++v) {
                 const int64_t row = r0 + 16 * u + 4 * v + hi;
                 const int col = 16 * J + lo;
-                if (!GUARD || (row < r_end && col < n)) Q[row * ldq + col] = y[J][v];
+                if (!GUARD || (row < r_end && col < n)) __builtin_nontemporal_store(y[J][v], &Q[row * ldq + col]);
             }
     }
 }
@@ -530,14 +531,14 @@ apply_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, i
                     if (vec_store) {
 #pragma unroll
                         for (int c = 0; c < NP; c += 2)
-                            *reinterpret_cast<f64x2*>(q + c) = f64x2{y[i][c], y[i][c + 1]};
+                            __builtin_nontemporal_store(f64x2{y[i][c], y[i][c + 1]}, reinterpret_cast<f64x2*>(q + c));
                         done = true;
                     }
                 }
                 if (!done) {
 #pragma unroll
                     for (int c = 0; c < NP; ++c)
-                        if (c < n) q[c] = y[i][c];
+                        if (c < n) __builtin_nontemporal_store(y[i][c], &q[c]);
                 }
             }
         }

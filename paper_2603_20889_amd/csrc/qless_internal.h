@@ -195,6 +195,30 @@ struct DeviceInfo {
 // on first use per device).
 const DeviceInfo& current_device_info();
 
+// Arguments of one launch of the TSQR fold kernel (stage 1 or a tree level):
+// wavefront w folds rows [w * rows_per_wave, ...) of X (m x n, ld ldx); each
+// workgroup writes one triangle at Y + block * ystride (ld ldy), with
+// normalise the diagonal made non-negative.  With Yinit (may alias Y), each
+// workgroup starts from its triangle there instead of zero (a running
+// stage-1 state over chunks of rows).
+struct FoldArgs {
+    const double* X;
+    int64_t m;
+    int n;
+    int64_t ldx, rows_per_wave, nwaves;
+    double* Y;
+    int64_t ldy, ystride;
+    int normalise;
+    const double* Yinit;
+};
+
+// Launch function of one compiled fold instance (tsqr_i*.hip).
+typedef hipError_t (*FoldFn)(const FoldArgs&, hipStream_t);
+// The instance of exactly this padded width and rows per lane (or null).
+FoldFn find_fold(int npad, int rpl);
+// Rows of one panel of an instance (the unit rows_per_wave is rounded to).
+int64_t tsqr_panel_rows(int npad, int rpl);
+
 // Plan of a TSQR call: stage-1 wave count, rows per wave, tree shape.
 struct TsqrPlan {
     int npad = 0;              // padded column count of the kernel instance
@@ -250,6 +274,26 @@ GramPlan make_gram_plan(int64_t m, int64_t n, int num_cus);
 // kernel then does not multiply.
 hipError_t launch_gram(const double* X, int64_t m, int64_t n, int64_t ldx, const double* M, bool m_upper,
                        double* Cpart, double* C, const GramPlan& plan, hipStream_t stream);
+
+// Double-double Gram pass (gram_dd.hip): k workgroups of 256 threads, each
+// over rows_per_block rows, writing a (hi, lo) partial of 2 n x n doubles.
+struct GramDdPlan {
+    int npad = 0;
+    int64_t rows_per_block = 0;
+    int64_t k = 0;
+    size_t part_bytes = 0;
+};
+GramDdPlan make_gram_dd_plan(int64_t m, int64_t n, int num_cus);
+// C = X^T X in double-double: hi into Chi, lo into Clo (may be null), ld ldc.
+hipError_t launch_gram_dd(const double* X, int64_t m, int64_t n, int64_t ldx, double* part, double* Chi, double* Clo,
+                          int64_t ldc, const GramDdPlan& plan, hipStream_t stream);
+// Upper Cholesky of the double-double C (n x n, ld n): R in double-double
+// (Rhi, Rlo) and R^{-1} rounded to double (Minv); *info = j on breakdown.
+hipError_t launch_chol_dd(const double* Chi, const double* Clo, int n, double* Rhi, double* Rlo, double* Minv,
+                          int* info, hipStream_t stream);
+// out = R2 (R1hi + R1lo) (double-double products, rounded), ld ldo.
+hipError_t launch_trmm_dd(const double* R2, const double* R1h, const double* R1l, int n, double* out, int64_t ldo,
+                          const int* info, hipStream_t stream);
 
 // Small n x n device steps (small.hip); every kernel runs as one workgroup.
 // Upper Cholesky C = R^T R with R^{-1}; sets *info = info_base + j on a

@@ -10,10 +10,7 @@ namespace qless {
 
 
 // Kernel instances (tsqr_i*.hip): launch_fold_np<NP>_r<RPL>.
-#define QLESS_DECL(NP, RPL)                                                                              \
-    hipError_t launch_fold_np##NP##_r##RPL(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, \
-                                           int64_t nw, double* Y, int64_t ldy, int64_t ystride,         \
-                                           int normalise, hipStream_t s);
+#define QLESS_DECL(NP, RPL) hipError_t launch_fold_np##NP##_r##RPL(const FoldArgs& a, hipStream_t s);
 #define QLESS_INSTANCES(X)                                                                          \
     X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5)              \
     X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)                     \
@@ -23,8 +20,7 @@ QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
 // One-workgroup last tree level, compiled for n <= 16 (launch_tree_np<NP>_r<RPL>).
 #define QLESS_TREE_DECL(NP, RPL)                                                                            \
-    hipError_t launch_tree_np##NP##_r##RPL(const double* Y, int64_t k, int n, double* stage, double* R,     \
-                                           int64_t ldr, hipStream_t s);
+    hipError_t launch_tree_np##NP##_r##RPL(const double* Y, int64_t k, int n, double* R, int64_t ldr, hipStream_t s);
 #define QLESS_TREE_INSTANCES(X)                                                                         \
     X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5) X(14, 4)      \
     X(16, 4) X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(16, 2) X(16, 3)
@@ -33,9 +29,7 @@ QLESS_TREE_INSTANCES(QLESS_TREE_DECL)
 
 namespace {
 
-typedef hipError_t (*FoldFn)(const double*, int64_t, int, int64_t, int64_t, int64_t, double*, int64_t, int64_t, int,
-                              hipStream_t);
-typedef hipError_t (*TreeFn)(const double*, int64_t, int, double*, double*, int64_t, hipStream_t);
+typedef hipError_t (*TreeFn)(const double*, int64_t, int, double*, int64_t, hipStream_t);
 
 struct Instance {
     int npad;
@@ -65,10 +59,16 @@ const TreeEntry kTrees[] = {
 // Matrix-core instance (tsqr_detail::mf_instance) and wavefronts per
 // workgroup of the fold kernel (tsqr_detail::waves_per_block).
 constexpr bool mf_instance_for(int np, int rpl) { return np > 16 && rpl == 1; }
+constexpr bool staged_instance_for(int np, int rpl) { return np <= 8 && rpl * np <= 40 && (rpl * np) % 2 == 0; }
 constexpr int waves_per_block_for(int np, int rpl) {
-    return (mf_instance_for(np, rpl) || (np * (np + 1) / 2 + np) * 8 * 4 > 65536) ? 2 : 4;
+    return staged_instance_for(np, rpl) ? tsqr_detail::kStagedWpb
+           : (mf_instance_for(np, rpl) || (np * (np + 1) / 2 + np) * 8 * 4 > 65536) ? 2 : 4;
 }
 static_assert(waves_per_block_for(8, 4) == tsqr_detail::waves_per_block<8, 4>() &&
+                  waves_per_block_for(1, 32) == tsqr_detail::waves_per_block<1, 32>() &&
+                  waves_per_block_for(1, 64) == tsqr_detail::waves_per_block<1, 64>() &&
+                  waves_per_block_for(7, 4) == tsqr_detail::waves_per_block<7, 4>() &&
+                  waves_per_block_for(16, 4) == tsqr_detail::waves_per_block<16, 4>() &&
                   waves_per_block_for(56, 8) == tsqr_detail::waves_per_block<56, 8>() &&
                   waves_per_block_for(64, 7) == tsqr_detail::waves_per_block<64, 7>() &&
                   waves_per_block_for(32, 1) == tsqr_detail::waves_per_block<32, 1>(),
@@ -137,6 +137,13 @@ int tsqr_tune_get(int64_t n, int* waves_per_cu, int* fan_in, int* rpl) {
     return QLESS_OK;
 }
 
+FoldFn find_fold(int npad, int rpl) {
+    const Instance* in = find_instance(npad, rpl);
+    return (in && in->npad == npad && in->rpl == rpl) ? in->fn : nullptr;
+}
+
+int64_t tsqr_panel_rows(int npad, int rpl) { return panel_rows_for(npad, rpl); }
+
 TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned) {
     TsqrPlan p;
     const Tuning t = (tuned && n >= 1 && n <= QLESS_MAX_N) ? g_tuning[n] : Tuning{};
@@ -197,13 +204,13 @@ hipError_t launch_tree(const Instance* in, const TsqrPlan& plan, double* src, do
     TreeFn tree = plan.block_tree ? find_tree(plan.npad, plan.rows_per_lane) : nullptr;
     hipError_t e = hipSuccess;
     while (e == hipSuccess && k > 1) {
-        if (tree && k * n <= (int64_t)tsqr_detail::kTreeWaves * plan.tree_rows) return tree(src, k, ni, dst, R, ldr, stream);
+        if (tree && k * n <= (int64_t)tsqr_detail::kTreeWaves * plan.tree_rows) return tree(src, k, ni, R, ldr, stream);
         const int64_t nw = ceil_div(k, plan.fan_in);
         const int64_t kn = ceil_div(nw, plan.wpb);
         if (kn == 1) {
-            e = in->fn(src, k * n, ni, n, rpw, nw, R, ldr, 0, 1, stream);
+            e = in->fn(FoldArgs{src, k * n, ni, n, rpw, nw, R, ldr, 0, 1, nullptr}, stream);
         } else {
-            e = in->fn(src, k * n, ni, n, rpw, nw, dst, n, nn, 0, stream);
+            e = in->fn(FoldArgs{src, k * n, ni, n, rpw, nw, dst, n, nn, 0, nullptr}, stream);
             double* t = src;
             src = dst;
             dst = t;
@@ -239,13 +246,13 @@ hipError_t launch_tsqr(const double* X, int64_t m, int64_t n, int64_t ldx, doubl
     hipError_t e;
     timing_begin(kTimeTsqrStage1, stream);
     if (plan.k1 == 1) {
-        e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, R, ldr, 0, 1, stream);
+        e = in->fn(FoldArgs{X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, R, ldr, 0, 1, nullptr}, stream);
         timing_end(kTimeTsqrStage1, stream);
         return e;
     }
     double* src = static_cast<double*>(work);
     double* dst = reinterpret_cast<double*>(static_cast<char*>(work) + plan.ybytes_a);
-    e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, stream);
+    e = in->fn(FoldArgs{X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, nullptr}, stream);
     timing_end(kTimeTsqrStage1, stream);
     if (e != hipSuccess) return e;
     return launch_tree(in, plan, src, dst, plan.k1, n, R, ldr, stream);
@@ -276,7 +283,7 @@ hipError_t launch_tsqr_update(const double* X, int64_t m, int64_t n, int64_t ldx
     hipError_t e = hipSuccess;
     if (m > 0) {
         timing_begin(kTimeTsqrStage1, stream);
-        e = in->fn(X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, stream);
+        e = in->fn(FoldArgs{X, m, (int)n, ldx, plan.rows_per_wave, plan.k0, src, n, nn, 0, nullptr}, stream);
         timing_end(kTimeTsqrStage1, stream);
         k = plan.k1;
     }
@@ -286,7 +293,7 @@ hipError_t launch_tsqr_update(const double* X, int64_t m, int64_t n, int64_t ldx
     if (e != hipSuccess) return e;
     ++k;
     if (k == 1) {   // no new rows: R([R]) is R with its diagonal made non-negative
-        return in->fn(src, n, (int)n, n, n, 1, R, ldr, 0, 1, stream);
+        return in->fn(FoldArgs{src, n, (int)n, n, n, 1, R, ldr, 0, 1, nullptr}, stream);
     }
     return launch_tree(in, plan, src, dst, k, n, R, ldr, stream);
 }

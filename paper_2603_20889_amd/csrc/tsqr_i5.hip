@@ -3,12 +3,6 @@
 #include "tsqr_kernels.h"
 
 namespace qless {
-hipError_t launch_fold_np48_r10(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
-    return tsqr_detail::launch_fold<48, 10>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
-}
-hipError_t launch_fold_np56_r8(const double* X, int64_t m, int n, int64_t ldx, int64_t rpw, int64_t nw,
-                               double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t s) {
-    return tsqr_detail::launch_fold<56, 8>(X, m, n, ldx, rpw, nw, Y, ldy, ystride, normalise, s);
-}
+QLESS_DEFINE_FOLD(48, 10)
+QLESS_DEFINE_FOLD(56, 8)
 }  // namespace qless

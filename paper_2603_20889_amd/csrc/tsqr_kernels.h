@@ -222,13 +222,6 @@ constexpr bool mf_instance() {
     return NP > 16 && RPL == 1;
 }
 
-// Wavefronts per workgroup of the fold kernel: 4, or 2 where four packed
-// triangles would take more than 64 KB of LDS.  The matrix-core instances
-// keep 2, since each wavefront also holds transposes in LDS.
-template <int NP, int RPL>
-constexpr int waves_per_block() {
-    return (mf_instance<NP, RPL>() || (tri_size<NP>() + NP) * 8 * 4 > 65536) ? 2 : 4;
-}
 
 // Panel loads for the layout of n <= 16: lane l gets rows base + l + 64 i
 // (i < RPL) into x[i][0..NP-1].
@@ -358,6 +351,20 @@ __device__ __forceinline__ void fold_panels_lane_private(const double* __restric
 template <int NP, int RPL>
 constexpr bool staged_instance() {
     return lane_private<NP>() && double_buffered<NP, RPL>() && (RPL * NP) % 2 == 0;
+}
+
+// Wavefronts per workgroup of the fold kernel: 8 for the LDS-staged
+// instances (n <= 8: one workgroup of 8 per CU holds eight 16-18 KB staging
+// buffers, and leaves half as many triangles for the tree as workgroups of
+// 4 would), 2 where four packed triangles would take more than 64 KB of LDS
+// and for the matrix-core instances (each wavefront also holds transposes in
+// LDS), else 4.
+constexpr int kStagedWpb = 8;
+
+template <int NP, int RPL>
+constexpr int waves_per_block() {
+    if constexpr (staged_instance<NP, RPL>()) return kStagedWpb;
+    return (mf_instance<NP, RPL>() || (tri_size<NP>() + NP) * 8 * 4 > 65536) ? 2 : 4;
 }
 
 __device__ __forceinline__ void wait_memory() {
@@ -830,6 +837,16 @@ __device__ __forceinline__ void zero_r(double* __restrict__ Rw, int lane) {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Load an n x n upper triangle (row-major, ld; entries below the diagonal
+// ignored) into the wavefront's packed R, which zero_r has cleared.
+template <int NP>
+__device__ __forceinline__ void load_r(double* __restrict__ Rw, int n, const double* __restrict__ src, int64_t ld,
+                                       int lane) {
+    for (int J = 0; J < n; ++J)
+        for (int c = J + lane; c < n; c += kWave) Rw[tri_row<NP>(J) + c - J] = src[(int64_t)J * ld + c];
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Write the wavefront's R (n x n, zeros below the diagonal) to out (ld).
 // With normalise, rows with a negative diagonal are negated and -0.0 is
 // written as +0.0.
@@ -891,7 +908,9 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
 }
 
 // The n = 64 matrix-core instance needs more than 256 registers per lane
-// (one wavefront per SIMD); every other instance is built for two.
+// (one wavefront per SIMD); every other instance is built for two.  (Three
+// per SIMD for the n = 16 fold with three rows per lane, at most 168
+// registers, measured 3 % slower than two with four rows per lane.)
 template <int NP, int RPL>
 constexpr int fold_waves_per_eu() {
     return (mf_instance<NP, RPL>() && NP > 48) ? 1 : 2;
@@ -909,10 +928,13 @@ template <int NP, int RPL>
 __global__ void __launch_bounds__((64 * waves_per_block<NP, RPL>()))
 __attribute__((amdgpu_waves_per_eu(fold_waves_per_eu<NP, RPL>())))
 tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
-                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int64_t ystride, int normalise) {
+                 int64_t nwaves, double* __restrict__ Y, int64_t ldy, int64_t ystride, int normalise,
+                 const double* Yinit) {
     constexpr int WPB = waves_per_block<NP, RPL>();
     constexpr int STRIDE = tri_size<NP>() + NP;
     constexpr int STAGE = mf_instance<NP, RPL>() ? kMfScratch : staged_instance<NP, RPL>() ? kWave * RPL * NP : 2;
+    static_assert((size_t)WPB * (STRIDE + STAGE) * sizeof(double) + 16 <= 160 * 1024,
+                  "a workgroup must fit the 160 KB of LDS of a gfx950 compute unit");
     __shared__ double Rsh[WPB][STRIDE];
     __shared__ __attribute__((aligned(16))) double stage[WPB][STAGE];
     __shared__ int arrivals;
@@ -926,6 +948,7 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     const int nvalid = (int)(nwaves - w0 < WPB ? nwaves - w0 : WPB);
     double* Rw = Rsh[wib];
     zero_r<NP>(Rw, lane);
+    if (Yinit != nullptr && wib == 0) load_r<NP>(Rw, n, Yinit + (int64_t)blockIdx.x * ystride, ldy, lane);
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
     fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane,
@@ -942,53 +965,60 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
 }
 
 template <int NP, int RPL>
-hipError_t launch_fold(const double* X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave, int64_t nwaves,
-                       double* Y, int64_t ldy, int64_t ystride, int normalise, hipStream_t stream) {
+hipError_t launch_fold(const FoldArgs& a, hipStream_t stream) {
     constexpr int WPB = waves_per_block<NP, RPL>();
-    const int64_t blocks = ceil_div(nwaves, WPB);
-    hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, X, m, n, ldx,
-                       rows_per_wave, nwaves, Y, ldy, ystride, normalise);
+    const int64_t blocks = ceil_div(a.nwaves, WPB);
+    hipLaunchKernelGGL((tsqr_fold_kernel<NP, RPL>), dim3((unsigned)blocks), dim3(64 * WPB), 0, stream, a.X, a.m, a.n,
+                       a.ldx, a.rows_per_wave, a.nwaves, a.Y, a.ldy, a.ystride, a.normalise, a.Yinit);
     return hipGetLastError();
 }
 
 // Last tree level of a TSQR for n <= 16 in one workgroup: wavefront w of
-// kTreeWaves folds a contiguous share of the k stacked triangles; the
-// wavefronts publish their triangles in `stage` (workgroup-scope ordering
-// through the barrier, all on one CU) and wavefront 0 folds those into R
-// with a non-negative diagonal.  Replaces the last two or three launches of
-// a fan-in tree.
+// kTreeWaves folds a contiguous share of the k stacked triangles into its
+// triangle in LDS; after the workgroup barrier wavefront 0 folds the others'
+// into its own, in wavefront order, and writes R with a non-negative
+// diagonal.  Replaces the last two or three launches of a fan-in tree.
 constexpr int kTreeWaves = 8;
 
 template <int NP, int RPL>
 __global__ void __launch_bounds__(64 * kTreeWaves) __attribute__((amdgpu_waves_per_eu(2)))
-tsqr_tree_block_kernel(const double* __restrict__ Y, int64_t k, int n, double* __restrict__ stage,
-                       double* __restrict__ R, int64_t ldr) {
+tsqr_tree_block_kernel(const double* __restrict__ Y, int64_t k, int n, double* __restrict__ R, int64_t ldr) {
     __shared__ double Rsh[kTreeWaves][tri_size<NP>() + NP];
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double* Rw = Rsh[w];
-    const int64_t nn = (int64_t)n * n;
     const int64_t per = ceil_div(k, kTreeWaves);
     const int64_t t0 = (int64_t)w * per < k ? (int64_t)w * per : k;
     const int64_t t1 = t0 + per < k ? t0 + per : k;
     zero_r<NP>(Rw, lane);
     fold_rows<NP, RPL>(Y, n, n, t0 * n, t1 * n, Rw, lane);
-    store_r<NP>(Rw, n, stage + w * nn, n, false, lane);
     __syncthreads();
     if (w == 0) {
-        zero_r<NP>(Rw, lane);
-        fold_rows<NP, RPL>(stage, n, n, 0, (int64_t)kTreeWaves * n, Rw, lane);
-        store_r<NP>(Rw, n, R, ldr, true, lane);
+        // the wavefronts' triangles stay in LDS: fold 1.. into 0, in order
+        fold_block_triangles<NP, RPL>(&Rsh[0][0], tri_size<NP>() + NP, kTreeWaves, n, lane);
+        store_r<NP>(Rsh[0], n, R, ldr, true, lane);
     }
 }
 
 template <int NP, int RPL>
-hipError_t launch_tree_block(const double* Y, int64_t k, int n, double* stage, double* R, int64_t ldr,
-                             hipStream_t stream) {
-    hipLaunchKernelGGL((tsqr_tree_block_kernel<NP, RPL>), dim3(1), dim3(64 * kTreeWaves), 0, stream, Y, k, n, stage,
-                       R, ldr);
+hipError_t launch_tree_block(const double* Y, int64_t k, int n, double* R, int64_t ldr, hipStream_t stream) {
+    hipLaunchKernelGGL((tsqr_tree_block_kernel<NP, RPL>), dim3(1), dim3(64 * kTreeWaves), 0, stream, Y, k, n, R, ldr);
     return hipGetLastError();
 }
 
 }  // namespace tsqr_detail
 }  // namespace qless
+
+// Definitions of the launch functions of one (padded width, rows per lane)
+// instance, for the instance files (one file per group of widths, so that
+// the instances compile in parallel).
+#define QLESS_DEFINE_FOLD(NP, RPL)                                                        \
+    hipError_t launch_fold_np##NP##_r##RPL(const FoldArgs& a, hipStream_t s) {             \
+        return tsqr_detail::launch_fold<NP, RPL>(a, s);                                   \
+    }
+#define QLESS_DEFINE_TREE(NP, RPL)                                                                            \
+    hipError_t launch_tree_np##NP##_r##RPL(const double* Y, int64_t k, int n, double* R, int64_t ldr,        \
+                                           hipStream_t s) {                                                  \
+        return tsqr_detail::launch_tree_block<NP, RPL>(Y, k, n, R, ldr, s);                                  \
+    }
+

@@ -28,22 +28,30 @@ struct CatSrc {
     int n;
 };
 
-// Element (row, c) of [Y X]; the caller guarantees row < m and c < p + n.
-__device__ __forceinline__ double cat_at(const CatSrc& s, int64_t row, int c) {
-    return c < s.p ? s.Y[row * s.ldy + c] : s.X[row * s.ldx + (c - s.p)];
+// Source of column c of [Y X]: its base pointer and row stride (null for a
+// padding column c >= p + n).  Chosen once per column, not per element.
+__device__ __forceinline__ const double* cat_col(const CatSrc& s, int c, int64_t& ld) {
+    if (c < s.p) {
+        ld = s.ldy;
+        return s.Y + c;
+    }
+    ld = s.ldx;
+    return c < s.p + s.n ? s.X + (c - s.p) : nullptr;
 }
 
 // Layout of n <= 16 (lane l holds rows base + l + 64 i, every column).
 template <int NP, int RPL>
 __device__ __forceinline__ void load_cat_1d(double (&x)[RPL][NP], const CatSrc& s, int64_t base, int64_t r_end,
                                             int lane) {
-    const int w = s.p + s.n;
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-        const int64_t row = base + lane + (int64_t)kWave * i;
-        const bool ok = row < r_end;
+    for (int c = 0; c < NP; ++c) {
+        int64_t ld;
+        const double* col = cat_col(s, c, ld);   // wave-uniform
 #pragma unroll
-        for (int c = 0; c < NP; ++c) x[i][c] = (ok && c < w) ? cat_at(s, row, c) : 0.0;
+        for (int i = 0; i < RPL; ++i) {
+            const int64_t row = base + lane + (int64_t)kWave * i;
+            x[i][c] = (col != nullptr && row < r_end) ? col[row * ld] : 0.0;
+        }
     }
 }
 
@@ -52,16 +60,15 @@ __device__ __forceinline__ void load_cat_1d(double (&x)[RPL][NP], const CatSrc& 
 template <int NP, int RPL>
 __device__ __forceinline__ void load_cat_2d(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
                                             int64_t r_end, int lane) {
-    const int w = s.p + s.n;
     const int rg = lane / kG2, cg = lane % kG2;
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-        const int64_t row = base + rg + (int64_t)kRG2 * i;
-        const bool ok = row < r_end;
+    for (int u = 0; u < NP / kG2; ++u) {
+        int64_t ld;
+        const double* col = cat_col(s, cg + kG2 * u, ld);
 #pragma unroll
-        for (int u = 0; u < NP / kG2; ++u) {
-            const int c = cg + kG2 * u;
-            x[i][u] = (ok && c < w) ? cat_at(s, row, c) : 0.0;
+        for (int i = 0; i < RPL; ++i) {
+            const int64_t row = base + rg + (int64_t)kRG2 * i;
+            x[i][u] = (col != nullptr && row < r_end) ? col[row * ld] : 0.0;
         }
     }
 }

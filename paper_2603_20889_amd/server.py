@@ -7,20 +7,23 @@ the data through the Q-less QR of the extended matrix).
 
 Serving loop (continuous batching, not a queue alone):
   * requests wait in an admission queue until their HBM footprint
-    (8 m (n+1) bytes of data plus the (n+1)^2 running R) fits the budget and
-    an active slot is free;
-  * every step folds a chunk of rows of each active request the step's byte
-    budget reaches into its running R (one batched launch, ``BatchPlan`` with
-    accumulate, or the single-matrix update calls back to back on one
-    stream), so work of requests that arrived at different times overlaps on
-    the device; requests with little work left get all of it and the rest of
-    the budget goes to the others oldest first, so short requests do not wait
-    behind long ones and long ones keep their arrival order;
-    R([R_old; chunk]) = R([rows so far; chunk]) makes the n x n R the whole
-    per-request state, and it stays on the device;
-  * a request whose rows are exhausted gets its back substitution on the
-    device, its result is read back and its memory is released, which admits
-    the next waiting requests.
+    (8 m (n+1) bytes of data plus the running state) fits the budget and an
+    active slot is free;
+  * every step gives rows to the active requests within the step's byte
+    budget: requests with little work left get all of it (smallest first)
+    and the rest of the budget goes to the others oldest first, so short
+    requests do not wait behind long ones and long ones keep their arrival
+    order; each chunk is folded into its request's state on the device
+    (by default a running Q-less TSQR whose stage-1 triangles stay in HBM
+    between steps, the tree running once when the rows are exhausted --
+    R([X_1; X_2; ...]) does not depend on the chunking), and the chunks of
+    different requests run on different streams, so their work overlaps on
+    the device;
+  * a request whose rows are exhausted gets its tree and back substitution
+    on the device and an asynchronous copy of its result to the host; the
+    loop keeps serving while the copy is on its way, and completes the
+    request (latency, memory back to the budget, admission of the next
+    waiting requests) when its event has fired.
 
 The executor does the device work (``GpuExecutor``, through libqless); the
 scheduling logic only calls its admit / step / finish methods, so tests can
@@ -62,23 +65,31 @@ class Request:
 
 
 class GpuExecutor:
-    """Device executor: request data and running R live in HBM.
+    """Device executor: request data and per-request state live in HBM.
 
+    mode "state" (default): each request keeps a running Q-less TSQR state on
+    the device (the stage-1 triangles of its plan, ``TsqrState``); a step
+    enqueues one stage-1 launch per request that got rows, and a finishing
+    request gets the tree, the back substitution and an asynchronous copy of
+    (x, |rho|) to pinned host memory, completed when its event has fired.
+    Requests are spread round-robin over ``streams`` HIP streams, so the
+    launches of different requests overlap on the device (one stream's
+    draining launch leaves compute units to the next one's); at most
+    ``inflight`` steps are enqueued ahead of the device.
+    mode "update": each step runs, per request, the single-matrix kernels on
+    its chunk with the previous R stacked in (``qless_tsqr_r_update``: a
+    full tree per chunk), on one stream, waiting for each finished request.
     mode "batched": each step is one persistent batched launch (plus tree
-    levels) over all active requests' chunks (``BatchPlan`` with accumulate).
-    mode "update": each step enqueues, per active request, the single-matrix
-    kernels on its chunk with the previous R stacked in
-    (``qless_tsqr_r_update``); the chunks of a step run back to back on one
-    stream, and the device is waited for when a result is read."""
+    levels) over all chunks (``BatchPlan`` with accumulate), built per step."""
 
     def __init__(self, device, tile_bytes: int = 1 << 20, data_fn: Optional[Callable] = None,
-                 mode: str = "batched", keep_r: bool = False):
+                 mode: str = "state", keep_r: bool = False, streams: int = 4, inflight: int = 2):
         import torch
 
         import paper_2603_20889_amd as q
         import workloads
-        if mode not in ("batched", "update"):
-            raise ValueError("mode must be 'batched' or 'update'")
+        if mode not in ("state", "batched", "update"):
+            raise ValueError("mode must be 'state', 'batched' or 'update'")
         self.q = q
         self.torch = torch
         self.device = device
@@ -86,6 +97,9 @@ class GpuExecutor:
         self.mode = mode
         self._data = data_fn or (lambda r: workloads.ls_request_data(r.m, r.n, r.seed, device=device)[0])
         self.stream = torch.cuda.current_stream(device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, streams))] if mode == "state" else []
+        self.inflight = max(1, inflight)
+        self._step_events = collections.deque()
         self.steps = 0
         self.keep_r = keep_r
         self._work = None
@@ -98,11 +112,31 @@ class GpuExecutor:
     def admit(self, r: Request):
         torch = self.torch
         Ab = self._data(r)
+        if self.mode == "state":
+            s = self.streams[r.id % len(self.streams)]
+            s.wait_stream(self.stream)           # the data is made on the default stream
+            Ab.record_stream(s)                   # and read on s: keep it until s is done with it
+            r.state = {"Ab": Ab, "stream": s, "st": self.q.TsqrState(r.m, r.n + 1, self.device, stream=s)}
+            return
         R = torch.zeros((r.n + 1, r.n + 1), dtype=torch.float64, device=self.device)
         r.state = {"Ab": Ab, "R": R}
 
     def step(self, chunks):
-        if self.mode == "update":
+        if self.mode == "state":
+            while len(self._step_events) >= self.inflight:     # bounded run-ahead of the host
+                for ev in self._step_events.popleft():
+                    ev.synchronize()
+            used = {}
+            for r, lo, hi in chunks:
+                r.state["st"].fold(r.state["Ab"][lo:hi])
+                used[id(r.state["stream"])] = r.state["stream"]
+            evs = []
+            for s in used.values():
+                ev = self.torch.cuda.Event()
+                ev.record(s)
+                evs.append(ev)
+            self._step_events.append(evs)
+        elif self.mode == "update":
             for r, lo, hi in chunks:
                 need = self.q.qless_workspace_bytes(self.q.QLESS_METHOD_TSQR_UPDATE, hi - lo, r.n + 1)
                 self.q.qless_tsqr_r_update(r.state["Ab"][lo:hi], r.state["R"], work=self._workspace(need))
@@ -122,16 +156,58 @@ class GpuExecutor:
         R = self.q.qless_tsqr_r(Ab)
         r.state = {"Ab": Ab, "R": R}
         self.steps += 1
-        self.finish(r)
+        self._read(r, *self.q.qless_lstsq_finish(R), R)
+
+    def finish_async(self, r: Request):
+        """Enqueue a finished request's tree and back substitution on its
+        stream with an asynchronous copy of the results to pinned memory;
+        returns a handle for poll / collect.  Modes other than "state"
+        finish at once (the handle is ready)."""
+        torch = self.torch
+        if self.mode != "state":
+            self.finish(r)
+            return None
+        s = r.state["stream"]
+        with torch.cuda.stream(s):
+            R = r.state["st"].finish()
+            x, res, info = self.q.qless_lstsq_finish(R)
+            hx = torch.empty(r.n, dtype=torch.float64, pin_memory=True)
+            hres = torch.empty(1, dtype=torch.float64, pin_memory=True)
+            hinfo = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            hx.copy_(x, non_blocking=True)
+            hres.copy_(res, non_blocking=True)
+            hinfo.copy_(info, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"ev": ev, "x": hx, "res": hres, "info": hinfo, "R": R, "dev": (x, res, info)}
+
+    def poll(self, handle) -> bool:
+        return handle is None or handle["ev"].query()
+
+    def collect(self, r: Request, handle):
+        if handle is None:
+            return
+        handle["ev"].synchronize()
+        r.x = handle["x"].numpy().copy()
+        r.resid = float(handle["res"][0])
+        r.info = int(handle["info"][0])
+        if self.keep_r:
+            r.R = handle["R"]
+        r.state = None
 
     def finish(self, r: Request):
-        x, res, info = self.q.qless_lstsq_finish(r.state["R"])
+        if self.mode == "state":
+            self.collect(r, self.finish_async(r))
+            return
+        self._read(r, *self.q.qless_lstsq_finish(r.state["R"]), r.state["R"])
+
+    def _read(self, r: Request, x, res, info, R):
         self.torch.cuda.current_stream(self.device).synchronize()
         r.x = x.cpu().numpy()
         r.resid = float(res.item())
         r.info = int(info.item())
         if self.keep_r:
-            r.R = r.state["R"]
+            r.R = R
         r.state = None
 
 
@@ -151,6 +227,7 @@ class LstsqServer:
         self.done: list[Request] = []
         self.rejected: list[Request] = []
         self.in_use = 0
+        self.finishing: list = []           # (request, executor handle) whose results are on their way
         self.max_queue = 0
         self.max_active_seen = 0
         self.t0 = 0.0
@@ -203,7 +280,22 @@ class LstsqServer:
             rows[r.id] = 1
         return [(r, r.rows_done, r.rows_done + rows[r.id]) for r in self.active if rows[r.id] > 0]
 
+    def _poll(self):
+        """Complete the finishing requests whose results have arrived; their
+        memory then goes back to the budget."""
+        still = []
+        for r, h in self.finishing:
+            if self.ex.poll(h):
+                self.ex.collect(r, h)
+                r.done_s = self.now()
+                self.in_use -= r.footprint
+                self.done.append(r)
+            else:
+                still.append((r, h))
+        self.finishing = still
+
     def step(self):
+        self._poll()
         self._admit()
         chunks = self._chunks()
         if not chunks:
@@ -214,13 +306,17 @@ class LstsqServer:
         still = []
         for r in self.active:                   # requests without rows this step stay active
             if r.rows_done >= r.m:
-                self.ex.finish(r)
-                r.done_s = self.now()
-                self.in_use -= r.footprint
-                self.done.append(r)
+                if hasattr(self.ex, "finish_async"):
+                    self.finishing.append((r, self.ex.finish_async(r)))
+                else:
+                    self.ex.finish(r)
+                    r.done_s = self.now()
+                    self.in_use -= r.footprint
+                    self.done.append(r)
             else:
                 still.append(r)
         self.active = still
+        self._poll()
         return True
 
     def run(self, requests, realtime: bool = True):
@@ -228,12 +324,14 @@ class LstsqServer:
         released by the wall clock; otherwise all arrive at t = 0."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
         self.t0 = self.clock()
-        while pending or self.queue or self.active:
+        while pending or self.queue or self.active or self.finishing:
             t = self.now()
             while pending and (not realtime or pending[0].arrival_s <= t):
                 self.submit(pending.popleft())
             if not self.step():
-                if pending:
+                if self.finishing:
+                    time.sleep(20e-6)             # results on their way: poll again soon
+                elif pending:
                     wait = pending[0].arrival_s - self.now()
                     if wait > 0:
                         time.sleep(min(wait, 0.001))
@@ -259,7 +357,8 @@ class LstsqServer:
 
 class FifoServer:
     """Baseline: one request at a time in arrival order, each solved by the
-    plain single-matrix call (no batching)."""
+    plain single-matrix call (no batching), its result read back before the
+    next one starts."""
 
     def __init__(self, executor, clock: Callable[[], float] = time.perf_counter):
         self.ex = executor

@@ -140,3 +140,47 @@ def test_q_from_r_argument_errors_on_host():
     assert need > 0
     assert lib.qless_q_from_r(FAKE, 100, 4, 4, FAKE, 4, FAKE, 4, NULL, NULL, need, NULL) == q.QLESS_ERR_WORKSPACE
     assert lib.svqb_q(FAKE, 100, 4, 4, NULL, 4, FAKE, 4, NULL, 0.0, NULL, FAKE, 1 << 30, NULL) == q.QLESS_ERR_ARG
+
+
+def test_running_state_argument_errors_on_host():
+    lib = q.load()
+    assert lib.qless_tsqr_state_bytes(100, 0) == 0 and lib.qless_tsqr_state_bytes(-1, 4) == 0
+    assert lib.qless_tsqr_state_bytes(100, 65) == 0
+    need = lib.qless_tsqr_state_bytes(10_000_000, 8)
+    assert need >= 8 * 8 * 8
+    assert lib.qless_tsqr_state_init(FAKE, need - 1, 10_000_000, 8, NULL) == q.QLESS_ERR_WORKSPACE
+    assert lib.qless_tsqr_state_init(NULL, need, 10_000_000, 8, NULL) == q.QLESS_ERR_WORKSPACE
+    assert lib.qless_tsqr_state_init(FAKE, need, 10_000_000, 65, NULL) == q.QLESS_ERR_UNSUPPORTED
+    assert lib.qless_tsqr_state_fold(NULL, 10, 8, FAKE, need, 10_000_000, 8, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_tsqr_state_fold(FAKE, 10, 7, FAKE, need, 10_000_000, 8, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_tsqr_state_fold(FAKE, 0, 8, FAKE, need, 10_000_000, 8, NULL) == q.QLESS_OK   # nothing to do
+    assert lib.qless_tsqr_state_finish(FAKE, need, 10_000_000, 8, NULL, 8, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_tsqr_state_finish(FAKE, need, 10_000_000, 8, FAKE, 7, NULL) == q.QLESS_ERR_ARG
+
+
+def test_wide_argument_errors_on_host():
+    lib = q.load()
+    assert lib.qless_wide_workspace_bytes(100, 200, 64) == 0          # m < n
+    assert lib.qless_wide_workspace_bytes(1000, 200, 65) == 0
+    need = lib.qless_wide_workspace_bytes(1000, 200, 64)
+    assert need > 0
+    assert lib.qless_wide_r(FAKE, 100, 200, 200, FAKE, 200, FAKE, 200, 64, NULL, FAKE, need, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_wide_r(FAKE, 1000, 200, 200, FAKE, 200, FAKE, 200, 65, NULL, FAKE, need, NULL) == \
+        q.QLESS_ERR_UNSUPPORTED
+    assert lib.qless_wide_r(FAKE, 1000, 200, 200, FAKE, 200, NULL, 200, 64, NULL, FAKE, need, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_wide_r(FAKE, 1000, 200, 200, FAKE, 200, FAKE, 200, 64, NULL, FAKE, need - 1, NULL) == \
+        q.QLESS_ERR_WORKSPACE
+
+
+def test_gram_entry_points_argument_errors_on_host():
+    lib = q.load()
+    assert lib.qless_gram(FAKE, 100, 0, 4, FAKE, 4, NULL, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_gram(FAKE, 100, 4, 4, FAKE, 3, NULL, FAKE, 1 << 20, NULL) == q.QLESS_ERR_ARG
+    assert lib.qless_gram(FAKE, 100, 65, 65, FAKE, 65, NULL, FAKE, 1 << 20, NULL) == q.QLESS_ERR_UNSUPPORTED
+    need = q.qless_workspace_bytes(q.QLESS_METHOD_GRAM, 10_000_000, 8)
+    assert need > 0
+    assert lib.qless_gram(FAKE, 10_000_000, 8, 8, FAKE, 8, NULL, FAKE, need - 1, NULL) == q.QLESS_ERR_WORKSPACE
+    need = q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2_DD, 10_000_000, 8)
+    assert need > q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2, 10_000_000, 8) // 4
+    assert lib.cholqr2_dd_r(FAKE, 10_000_000, 8, 8, FAKE, 8, NULL, FAKE, need - 1, NULL) == q.QLESS_ERR_WORKSPACE
+    assert lib.cholqr2_dd_r(FAKE, 100, 8, 7, FAKE, 8, NULL, FAKE, need, NULL) == q.QLESS_ERR_ARG

@@ -501,3 +501,20 @@ def test_two_phase_of_a_vector_in_the_span_leaves_nothing():
     X = Y @ g.standard_normal((4, 3))
     _, R = oracle.two_phase_r(Y, X)
     assert np.linalg.norm(R) <= 1e-14 * np.linalg.norm(X)
+
+
+def test_row_scaled_metric_sees_a_wrong_trailing_row():
+    """The row-wise metric of the parity tests flags an error in the smallest
+    row that the normwise e_R cannot see: X = Q0 diag(sigma) with sigma from
+    1 down to 1e-4 has R = diag(sigma), and a 1e-9 relative error in R_nn
+    moves e_R by only 1e-13."""
+    sig = wl.logspace_sigma(8, 4)
+    X = wl.orthonormal_columns(20000, 8, wl.rng(5)) * sig
+    Ro = oracle.householder_r(X)
+    assert np.allclose(np.abs(np.diag(Ro)), sig, rtol=1e-12)
+    bad = Ro.copy()
+    bad[-1, -1] *= 1.0 + 1e-9
+    floor = 1e-4 * oracle.col_norm_max(X)
+    assert oracle.rel_err_r(bad, Ro) <= 1e-12
+    assert oracle.row_scaled_err(bad, Ro, floor) > 2e-11
+    assert oracle.row_scaled_err(oracle.cholqr2_r(X)[0], Ro, floor) <= 2e-11

@@ -33,7 +33,7 @@ class BudgetCheckingServer(LstsqServer):
     def step(self):
         ok = super().step()
         assert self.in_use <= self.budget
-        assert sum(r.footprint for r in self.active) == self.in_use
+        assert sum(r.footprint for r in self.active) + sum(r.footprint for r, _ in self.finishing) == self.in_use
         return ok
 
 
@@ -109,3 +109,34 @@ def test_short_requests_bypass_and_long_ones_keep_order():
     assert first[0] > 0 and 1 not in first     # the oldest long one takes the rest
     assert a.done_s <= b.done_s
     assert all(c.done_s <= r.done_s for r in (a, b))
+
+
+class AsyncOracleExecutor(OracleExecutor):
+    """Completes a finished request only after its handle has been polled a
+    few times, as the GPU executor's event-driven finish does."""
+
+    def __init__(self, delay=3):
+        super().__init__()
+        self.delay = delay
+
+    def finish_async(self, r):
+        return {"left": self.delay}
+
+    def poll(self, h):
+        h["left"] -= 1
+        return h["left"] < 0
+
+    def collect(self, r, h):
+        self.finish(r)
+
+
+def test_async_finish_keeps_serving_and_accounts_memory():
+    reqs = small_requests(14, seed=21)
+    budget = 3 * max(r.footprint for r in reqs)
+    srv = BudgetCheckingServer(AsyncOracleExecutor(), hbm_budget_bytes=budget, step_bytes=400_000)
+    st = srv.run(reqs, realtime=False)
+    assert st["completed"] == len(reqs) and srv.in_use == 0 and not srv.finishing
+    for r in reqs:
+        xo, reso = oracle.lstsq_from_r(oracle.householder_r(wl.ls_request_data(r.m, r.n, r.seed)[0]))
+        assert np.linalg.norm(r.x - xo) <= 1e-10 * np.linalg.norm(xo)
+        assert r.done_s >= r.admit_s >= r.arrival_s

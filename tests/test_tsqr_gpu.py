@@ -4,12 +4,17 @@ Bar (element-wise comparison of the full R on identical seeded inputs):
 e_R = ||R - R_oracle||_F / ||R_oracle||_F <= 1e-12 for kappa <= 1e4, and the
 Gram residual ||X^T X - R^T R||_F / ||X||_2^2 <= 1e-13 (X^T X from Dot2).
 Row by row, every entry must also be within E_ROW of the oracle relative to
-that row's diagonal entry, |R - R_oracle|_ij <= E_ROW |R_oracle|_ii: the
-normwise e_R is dominated by the large leading rows, so a wrong small
-trailing row (R_nn ~ 1e-4 at kappa = 1e4) would pass it.  E_ROW = 5e-12 is
-u * kappa * about 20 at kappa = 1e4; two independent CPU references (the
-Householder and the CholQR2 oracle) differ by up to 7.5e-13 in this measure
-on the kappa = 1e4 known-R inputs, and by about u at kappa = 1.
+that row's scale, |R - R_oracle|_ij <= E_ROW max(|R_oracle|_ii, 1e-4 c) with
+c the largest column norm of X: the normwise e_R is dominated by the large
+leading rows, so a wrong small trailing row (R_nn ~ 1e-4 at kappa = 1e4)
+would pass it; the floor keeps the bar at what kappa = 1e4 allows where the
+input is worse conditioned relative to its largest column.  A backward
+stable R has |dR_ij| <= c' n u ||X||_2, so against that floor the measure is
+at most about 1e4 c' n u (1.1e-12 c' n).  E_ROW = 2e-11 is 3x the largest
+value seen between two correct methods (6.2e-12: GPU against oracle on the
+two-phase inputs; 7.5e-13 between the Householder and the CholQR2 oracle at
+kappa = 1e4), and a 1e-8 relative error in a trailing row of R_nn ~ 1e-4,
+which e_R <= 1e-12 lets through, exceeds it 500-fold.
 At full benchmark sizes, where the oracle is too slow, the known-answer
 property R(Q0 R0) = R0 is checked instead.
 """
@@ -25,7 +30,7 @@ pytestmark = pytest.mark.gpu
 
 E_R = 1e-12
 E_G = 1e-13
-E_ROW = 5e-12
+E_ROW = 2e-11
 
 
 def run(X_np, dev, ldx_pad=0):
@@ -45,7 +50,7 @@ def check(X, R, tol_r=E_R, tol_g=E_G, tol_row=E_ROW):
     Ro = oracle.householder_r(X)
     e_r = oracle.rel_err_r(R, Ro)
     e_g = oracle.gram_residual(X, R)
-    e_row = oracle.row_scaled_err(R, Ro)
+    e_row = oracle.row_scaled_err(R, Ro, 1e-4 * oracle.col_norm_max(X))
     assert np.all(np.tril(R, -1) == 0.0)
     assert np.all(np.diag(R) >= 0.0)
     assert not np.signbit(R[np.triu_indices(R.shape[0])][R[np.triu_indices(R.shape[0])] == 0]).any()
@@ -102,7 +107,7 @@ def test_known_r_conditioning(gpu, n, k):
     if k <= 4:
         check(X, R)
         assert oracle.rel_err_r(R, R0) <= E_R
-        assert oracle.row_scaled_err(R, R0) <= E_ROW
+        assert oracle.row_scaled_err(R, R0, 1e-4 * oracle.col_norm_max(X)) <= E_ROW
     else:  # kappa = 1e8: beyond the 1e4 bar; still backward stable
         assert oracle.gram_residual(X, R) <= E_G
         assert oracle.rel_err_r(R, oracle.householder_r(X)) <= 1e-10
@@ -289,3 +294,38 @@ def test_binding_rejects_bad_outputs_before_launch(gpu):
         q.qless_tsqr_r(X, R=torch.empty((4, 4), dtype=torch.float64))   # host memory
     with pytest.raises(TypeError):
         q.cholqr2_r(X, info=torch.empty(1, dtype=torch.int64, device=gpu))
+
+
+@pytest.mark.parametrize("m_total,n,chunks", [
+    (1_000_000, 8, [1, 300_000, 0, 99_999, 600_000]),
+    (5_000_000, 16, [2_500_000, 2_500_000]),
+    (400_000, 33, [100_000] * 4),
+    (2_000_000, 48, [1_500_000, 123, 499_877]),
+    (300, 5, [100, 200]),                       # one stage-1 triangle in all
+    (0, 4, []),
+])
+def test_running_state_matches_oracle(gpu, m_total, n, chunks):
+    """qless_tsqr_state_*: the rows folded chunk by chunk into the device
+    state, one tree at the end, give the R of all rows at once (Alg. 2)."""
+    print("case running state m=%d n=%d chunks=%d" % (m_total, n, len(chunks)), flush=True)
+    X = wl.gaussian(m_total, n, seed=300 + n)
+    Xd = torch.from_numpy(X).to(gpu)
+    st = q.TsqrState(m_total, n, gpu)
+    lo = 0
+    for c in chunks:
+        st.fold(Xd[lo:lo + c])
+        lo += c
+    R = st.finish()
+    torch.cuda.synchronize(gpu)
+    R = R.cpu().numpy()
+    if m_total == 0:
+        assert np.array_equal(R, np.zeros((n, n)))
+    else:
+        check(X, R)
+    # the state is consumed: init again and reuse it on the same rows in one chunk
+    st.init()
+    st.fold(Xd)
+    R2 = st.finish()
+    torch.cuda.synchronize(gpu)
+    if m_total:
+        check(X, R2.cpu().numpy())
