@@ -97,6 +97,25 @@ int qless_tsqr_r(const double *X, int64_t m, int64_t n, int64_t ldx,
                  hipStream_t stream);
 
 /*
+ * qless_tsqr_r_noalloc -- qless_tsqr_r for callers that cannot allocate
+ * device memory or pass a workspace (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The same launches and
+ * results as qless_tsqr_r; the stacked triangles live in a library-owned
+ * device array of qless_noalloc_scratch_bytes() bytes (64 MiB: the largest
+ * plan on a 256-CU device, n = 64), one copy per GPU the library runs on,
+ * held until the process ends; its device address is looked up on the
+ * first call made with a device current.  Allocates nothing; a plan larger
+ * than the array returns QLESS_ERR_WORKSPACE.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on one GPU (different streams or
+ * host threads) race and must be ordered by the caller; nothing in the
+ * array needs clearing between calls.  Other arguments and errors as for
+ * qless_tsqr_r.
+ */
+size_t qless_noalloc_scratch_bytes(void);
+int qless_tsqr_r_noalloc(const double *X, int64_t m, int64_t n, int64_t ldx,
+                         double *R, int64_t ldr, hipStream_t stream);
+
+/*
  * qless_tsqr_r_update -- running R over chunks of rows: R <- R([R; X]), the
  * Q-less R of the previous rows stacked on the new ones (Alg. 2 applied to
  * the stack, Sec. 1: the R of all rows seen so far).  R (n x n, ldr, upper

@@ -45,7 +45,7 @@ EXPORTED = (
     "qless_tsqr_r_batched", "qless_tune_set", "qless_tune_get", "qless_q_from_r", "svqb_q",
     "qless_two_phase_r", "qless_two_phase_workspace_bytes", "qless_tsqr_state_bytes", "qless_tsqr_state_init",
     "qless_tsqr_state_fold", "qless_tsqr_state_finish", "qless_wide_r", "qless_wide_workspace_bytes",
-    "qless_gram", "cholqr2_dd_r",
+    "qless_gram", "cholqr2_dd_r", "qless_tsqr_r_noalloc", "qless_noalloc_scratch_bytes",
 )
 
 
@@ -134,6 +134,10 @@ def load() -> ctypes.CDLL:
     lib.qless_tune_set.restype = ctypes.c_int
     lib.qless_tune_get.argtypes = [i64, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.qless_tune_get.restype = ctypes.c_int
+    lib.qless_tsqr_r_noalloc.argtypes = [vp, i64, i64, i64, vp, i64, vp]
+    lib.qless_tsqr_r_noalloc.restype = ctypes.c_int
+    lib.qless_noalloc_scratch_bytes.argtypes = []
+    lib.qless_noalloc_scratch_bytes.restype = sz
     lib.qless_timing_enable.argtypes = [ctypes.c_int]
     lib.qless_timing_enable.restype = ctypes.c_int
     lib.qless_timing_reset.argtypes = []
