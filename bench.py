@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+TUNE_TABLE = os.path.join(ROOT, "paper_2603_20889_amd", "tuning_gfx950.json")
 FP64_PEAK_TFS = 78.6        # MI355X FP64 vector, published
 
 
@@ -144,6 +145,13 @@ def main() -> int:
                     help="launch-parameter overrides n:rows_per_lane[:waves_per_cu[:fan_in]],... "
                          "(qless_tune_set) applied before any timing, e.g. 32:1,64:1 for the "
                          "matrix-core fold")
+    ap.add_argument("--tune-table", type=str, default=TUNE_TABLE,
+                    help="autotuner table (JSON written by --autotune) applied before any timing; "
+                         "'' for the library defaults")
+    ap.add_argument("--autotune", type=str, default="",
+                    help="run the autotuner for these n (comma list) first and write its table to this "
+                         "path (--autotune-out), then apply it")
+    ap.add_argument("--autotune-out", type=str, default="gpurun_out/tuning_gfx950.json")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -164,6 +172,26 @@ def main() -> int:
     m, n = args.m, args.n
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     tuned = {}
+    tune_src = None
+    if args.autotune:
+        from paper_2603_20889_amd import autotune
+        ns_t = [int(v) for v in args.autotune.split(",") if v]
+        log("autotuning n = %s" % ns_t)
+        table = autotune.tune_tsqr(ns_t, device=dev, log=log)
+        os.makedirs(os.path.dirname(os.path.abspath(args.autotune_out)), exist_ok=True)
+        with open(args.autotune_out, "w") as f:
+            json.dump({"arch": "gfx950", "kernel_hash": kernel_source_hash(),
+                       "table": {str(k): v for k, v in table.items()}}, f, indent=1, sort_keys=True)
+        tune_src = args.autotune_out
+    elif args.tune_table and os.path.exists(args.tune_table):
+        tune_src = args.tune_table
+    if tune_src:
+        data = json.load(open(tune_src))
+        for k, v in data["table"].items():
+            q.qless_tune_set(int(k), int(v["waves_per_cu"]), int(v["fan_in"]), int(v["rows_per_lane"]))
+            tuned[int(k)] = q.qless_tune_get(int(k))
+        log("tuning table %s applied (taken on kernel sources %s, now %s)" %
+            (tune_src, data.get("kernel_hash"), kernel_source_hash()))
     for item in filter(None, args.tune.split(",")):
         f = [int(v) for v in item.split(":")] + [0, 0]
         q.qless_tune_set(f[0], f[2], f[3], f[1])
@@ -222,6 +250,7 @@ def main() -> int:
         "accuracy": {"e_R_vs_R0": e_r},
         "kernel_hash": kernel_source_hash(),
         "tuning_overrides": {str(k): v for k, v in tuned.items()} or None,
+        "tuning_table": os.path.relpath(tune_src, ROOT) if tune_src else None,
         "pct_hbm_peak_step": round(100.0 * value / HBM_PEAK_GBS, 2),
     }
 
@@ -273,6 +302,34 @@ def main() -> int:
                           "e_R_vs_R0": float(np.linalg.norm(Rc - R0) / np.linalg.norm(R0)),
                           "info": int(res[-1].item())}
             log(json.dumps(comp[name]))
+        # the explicit Q of Sec. 1 from X and the Q-less R (one pass: read X, write Q),
+        # next to a plain device copy of the same bytes (the read + write ceiling)
+        log("compare q_from_r")
+        Q = torch.empty_like(X)
+        qinfo = torch.empty(1, dtype=torch.int32, device=dev)
+        qwork, _ = q._workspace(q.QLESS_METHOD_Q_FROM_R, m, n, dev)
+        qf_ms, _ = time_calls(lambda: q.qless_q_from_r(X, R, Q=Q, info=qinfo, work=qwork), max(5, args.steps // 3), 2)
+        cp_ms, _ = time_calls(lambda: Q.copy_(X), max(5, args.steps // 3), 2)
+        q.qless_q_from_r(X, R, Q=Q, info=qinfo, work=qwork)
+        Qs = Q[:200_000].cpu().numpy()
+        Xs_ = X[:200_000].cpu().numpy()
+        comp["q_from_r"] = {"ms": round(qf_ms, 5), "bytes": 2 * nbytes,
+                            "GBps": round(2 * nbytes / (qf_ms * 1e-3) / 1e9, 1),
+                            "frac_hbm": round(2 * nbytes / (qf_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "copy_ms": round(cp_ms, 5), "copy_GBps": round(2 * nbytes / (cp_ms * 1e-3) / 1e9, 1),
+                            "frac_of_copy": round(cp_ms / qf_ms, 4), "info": int(qinfo.item()),
+                            "QR_minus_X_rel_sample": float(np.linalg.norm(Qs @ R.cpu().numpy() - Xs_) /
+                                                           np.linalg.norm(Xs_))}
+        log(json.dumps(comp["q_from_r"]))
+        del Q, Qs, Xs_, qwork
+        log("compare cholqr2_dd")
+        dd_ms, _ = time_calls(lambda: q.cholqr2_dd_r(X), max(5, args.steps // 3), 2)
+        Rd, dinfo = q.cholqr2_dd_r(X)
+        torch.cuda.synchronize()
+        comp["cholqr2_dd"] = {"ms": round(dd_ms, 5), "passes_over_X": 2,
+                              "e_R_vs_R0": float(np.linalg.norm(Rd.cpu().numpy() - R0) / np.linalg.norm(R0)),
+                              "info": int(dinfo.item())}
+        log(json.dumps(comp["cholqr2_dd"]))
         comp["tsqr_speedup_vs_svqb2"] = round(comp["svqb2"]["ms"] / ms, 3)
         comp["tsqr_speedup_vs_cholqr2"] = round(comp["cholqr2"]["ms"] / ms, 3)
         out["compare"] = comp
@@ -294,7 +351,7 @@ def main() -> int:
     if not args.no_sweep:
         out["sweep"] = bench_sweep(q, wl, dev, log, [int(v) for v in args.ns.split(",") if v],
                                    ks=tuple(int(v) for v in args.sweep_ks.split(",") if v),
-                                   cpu_threads=cpu_threads)
+                                   cpu_threads=cpu_threads, tuned=tuned)
 
     if not args.no_batched:
         out["batched"] = bench_batched(q, wl, dev, log)
@@ -311,7 +368,7 @@ CPU_SWEEP_MAX_N_ALL = 32
 CPU_SWEEP_MAX_N_ONE = 8
 
 
-def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads=None):
+def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads=None, tuned=None):
     """Column sweep m = 2^25, n in ns, sigma log-spaced to 10^-k, k in ks
     (default {0, 4, 8}): accuracy of TSQR and CholQR2 for every (n, k); timing
     (k = 4) of the TSQR launch (HIP events around it) and of the whole
@@ -322,6 +379,9 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads
     sweep = []
     for ns in ns:
         rec = {"n": ns, "m": m, "rows_per_lane": q.qless_tune_get(ns)["rows_per_lane"]}
+        tuned_n = q.qless_tune_get(ns) if tuned and ns in tuned else None
+        if tuned_n is not None:
+            rec["tuned"] = tuned_n
         for k in ks:
             log("sweep m=2^25 n=%d k=%d" % (ns, k))
             Xs, R0s = wl.config3(ns, k, m=m, device=dev)
@@ -350,6 +410,27 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads
                 k_ms, k_cnt = q.timing_read("tsqr_stage1")
                 q.timing_reset()
                 k_avg = k_ms / max(k_cnt, 1)
+                if tuned_n is not None:
+                    # the same calls with the library defaults, for tuned against default
+                    # (stage-1 kernel time; the whole call where no flush is interleaved)
+                    q.qless_tune_set(ns, 0, 0, 0)
+                    wd, _ = q._workspace(q.QLESS_METHOD_TSQR, m, ns, dev)
+
+                    def fd():
+                        if flush is not None:
+                            torch.sum(flush)
+                        q.qless_tsqr_r(Xs, R=Rs, work=wd)
+                    q.timing_reset()
+                    q.timing_enable(True)
+                    d_ms, _ = time_calls(fd, steps, 2)
+                    q.timing_enable(False)
+                    dk_ms, dk_cnt = q.timing_read("tsqr_stage1")
+                    q.timing_reset()
+                    q.qless_tune_set(ns, tuned_n["waves_per_cu"], tuned_n["fan_in"], tuned_n["rows_per_lane"])
+                    rec["tsqr_ms_default"] = round(dk_ms / max(dk_cnt, 1), 5)
+                    if flush is None:
+                        rec["tsqr_step_ms_default"] = round(d_ms, 5)
+                    del wd
                 gbs = tsqr_bytes(m, ns) / (k_avg * 1e-3) / 1e9
                 rec.update({"tsqr_ms": round(k_avg, 5), "tsqr_GBps": round(gbs, 1),
                             "tsqr_frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
@@ -387,21 +468,16 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads
 
 
 def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
-    """512 matrices (m log-uniform [1e4, 1e7], n in {4, 8, 16, 32}), each an
-    iid N(0,1) window of one device pool, in one persistent launch (eager and
-    replayed from a captured graph) vs one qless_tsqr_r launch per matrix."""
-    import numpy as np
+    """512 independent matrices (m log-uniform [1e4, 1e7], n in {4, 8, 16,
+    32}, iid N(0,1), each its own device allocation) in one persistent
+    stage-1 launch per width class plus the tree levels (eager and replayed
+    from a captured graph) vs one qless_tsqr_r launch sequence per matrix."""
     import torch
     shapes = wl.batched_shapes(count, seed)
-    pool_len = max(m * n for m, n in shapes)
-    pool = wl.gaussian_torch(pool_len, 1, seed=seed, device=dev).view(-1)
-    g = wl.rng(seed + 1)
-    Xs = []
-    for m, n in shapes:
-        off = int(g.integers(0, pool_len - m * n + 1))
-        Xs.append(pool[off:off + m * n].view(m, n))
+    Xs = [wl.gaussian_torch(m, n, seed=seed * 100_000 + i, device=dev) for i, (m, n) in enumerate(shapes)]
+    torch.cuda.synchronize()
     total_bytes = sum(8 * m * n for m, n in shapes)
-    log("batched: %d matrices, %.1f GB" % (count, total_bytes / 1e9))
+    log("batched: %d independent matrices, %.1f GB" % (count, total_bytes / 1e9))
     plan = q.BatchPlan(Xs)
     plan.run()
     torch.cuda.synchronize()
@@ -424,7 +500,11 @@ def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
             q.qless_tsqr_r(X, R=R, work=work)
     t_single, _ = time_calls(singles, 3, 1)
     err = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(Rb, Rs1))
-    res = {"matrices": count, "total_GB": round(total_bytes / 1e9, 2), "tiles": plan.tiles,
+    by_width = {}
+    for m, n in shapes:
+        by_width[n] = by_width.get(n, 0) + 8 * m * n
+    res = {"matrices": count, "independent_allocations": True, "total_GB": round(total_bytes / 1e9, 2),
+           "GB_by_n": {str(k): round(v / 1e9, 2) for k, v in sorted(by_width.items())}, "tiles": plan.tiles,
            "batched_ms": round(t_eager, 3), "batched_graph_ms": round(t_graph, 3),
            "single_launches_ms": round(t_single, 3),
            "solves_per_s": round(count / (t_graph * 1e-3), 1),
@@ -433,7 +513,7 @@ def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
            "max_rel_diff_vs_single": err}
     plan.close()
     log("batched: %s" % json.dumps(res))
-    del Xs, pool, work
+    del Xs, work
     torch.cuda.empty_cache()
     return res
 

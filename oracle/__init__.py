@@ -22,7 +22,10 @@ Paper: Thies & Roehrig-Zoellner, arXiv 2603.20889.
   lstsq_from_r  : least squares via the Q-less R of [A b], Sec. 1
   q_from_r      : explicit Q = X R^{-1} rebuilt from X and the Q-less R, Sec. 1
   two_phase_r   : R of (I - Y Y^T) X and B = Y^T X, the two-phase problem of Sec. 2
-  gram_dot2     : X^T X in twice-working precision (error metric only)
+  gram_dot2     : X^T X in twice-working precision (the Gram-residual metric and
+                  the reference of the GPU's double-double Gram)
+Metrics: rel_err_r (normwise e_R), row_scaled_err (row-wise, floored at a
+given scale), col_norm_max, gram_residual (e_G).
 """
 from __future__ import annotations
 

@@ -16,6 +16,7 @@
 // its root (R([R_old; X])), which is how a caller keeps a running R over
 // chunks of rows.
 #include <algorithm>
+#include <array>
 #include <new>
 #include <vector>
 
@@ -23,14 +24,13 @@
 
 struct qless_batch_plan {
     std::vector<qless::BatchMat> mats;
-    std::vector<int2> tiles;                  // (matrix, tile) longest first
-    std::vector<qless::BatchGroup> groups;    // tree groups, level by level
-    std::vector<int64_t> level_end;           // groups [level_end[l-1], level_end[l]) form level l
-    int np_max = 1;
-    bool has_staged = false;                  // some matrix uses an LDS-staged instance (n <= 8)
+    std::vector<int2> tiles;                  // (matrix, tile): by width class, longest first within a class
+    std::vector<qless::BatchGroup> groups;    // tree groups, by level, then by width class
+    int64_t tile_end[qless::batch_detail::kBatchClasses] = {};          // class c: tiles [end[c-1], end[c])
+    std::vector<std::array<int64_t, qless::batch_detail::kBatchClasses>> level_end;   // per level and class
+    int np_max[qless::batch_detail::kBatchClasses] = {};
     int64_t slot_doubles = 0;
     size_t off_tiles = 0, off_groups = 0, off_slots = 0, bytes = 0;
-    int64_t nwaves = 0;
     int waves_cap = 0;
 };
 
@@ -67,13 +67,24 @@ int64_t batch_panel_rows(int np) {
 
 }  // namespace
 
-hipError_t launch_batched_stage(const BatchMat* mats, const int2* tiles, int64_t ntiles, int64_t nwaves,
+hipError_t launch_batched_stage(int cls, const BatchMat* mats, const int2* tiles, int64_t ntiles, int64_t nwaves,
                                 double* slots, int r_doubles, bool staged, hipStream_t s);
-hipError_t launch_batched_tree(const BatchMat* mats, const BatchGroup* groups, int64_t ngroups, int64_t nwaves,
-                               double* slots, int r_doubles, hipStream_t s);
+hipError_t launch_batched_tree(int cls, const BatchMat* mats, const BatchGroup* groups, int64_t ngroups,
+                               int64_t nwaves, double* slots, int r_doubles, hipStream_t s);
+
+// Tree fan-in of a matrix of n columns: the single-matrix plan's (one panel
+// of stacked triangles per wavefront for n <= 16, else 4, or the autotuner's
+// choice), within [2, 64].
+int batch_fan_in(int64_t n) {
+    int fan = 0;
+    if (tsqr_tune_get(n, nullptr, &fan, nullptr) != QLESS_OK || fan < 2) fan = kFanIn;
+    return std::min(fan, 64);
+}
 
 int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_bytes, int waves_per_cu,
                       qless_batch_plan** out) {
+    using batch_detail::batch_class;
+    using batch_detail::kBatchClasses;
     if (out == nullptr || d == nullptr || count < 1) return QLESS_ERR_ARG;
     *out = nullptr;
     if (tile_bytes <= 0) tile_bytes = 4 << 20;
@@ -87,8 +98,10 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
     qless_batch_plan* p = new (std::nothrow) qless_batch_plan;
     if (!p) return QLESS_ERR_ARG;
     int64_t slots = 0;
-    std::vector<std::pair<int64_t, int2>> order;
-    std::vector<std::vector<BatchGroup>> levels;
+    // (class, rows * n, (matrix, tile)) for the tile order
+    std::vector<std::pair<std::pair<int, int64_t>, int2>> order;
+    // levels[l][c]: groups of tree level l + 1 in width class c
+    std::vector<std::array<std::vector<BatchGroup>, kBatchClasses>> levels;
     for (int32_t i = 0; i < count; ++i) {
         BatchMat M{};
         M.X = d[i].X;
@@ -99,6 +112,8 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
         M.n = (int)d[i].n;
         M.np = batch_np(d[i].n);
         M.accumulate = d[i].accumulate ? 1 : 0;
+        const int cls = batch_class(M.np);
+        const int fan = batch_fan_in(d[i].n);
         const int64_t panel = batch_panel_rows(M.np);
         int64_t tr = tile_bytes / (8 * d[i].n);
         tr = std::max<int64_t>(panel, tr / panel * panel);
@@ -111,36 +126,44 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
         int64_t base = slots, c = M.ntiles;
         if (c > 1) slots += c * nn;
         for (int l = 1; c > 1; ++l) {
-            const int64_t cn = ceil_div(c, kFanIn);
+            const int64_t cn = ceil_div(c, fan);
             const int64_t next_base = slots;
             if (cn > 1) slots += cn * nn;
             if ((int)levels.size() < l) levels.resize(l);
             for (int64_t g = 0; g < cn; ++g) {
                 BatchGroup G;
-                G.src = base + g * kFanIn * nn;
+                G.src = base + g * fan * nn;
                 G.dst = cn == 1 ? -1 : next_base + g * nn;
                 G.mat = i;
-                G.gsize = (int)std::min<int64_t>(kFanIn, c - g * kFanIn);
-                levels[l - 1].push_back(G);
+                G.gsize = (int)std::min<int64_t>(fan, c - g * fan);
+                levels[l - 1][cls].push_back(G);
             }
             base = next_base;
             c = cn;
         }
-        p->np_max = std::max(p->np_max, M.np);
-        if (M.np <= 8) p->has_staged = true;
+        p->np_max[cls] = std::max(p->np_max[cls], M.np);
         p->mats.push_back(M);
         for (int t = 0; t < M.ntiles; ++t) {
             const int64_t rows = std::min<int64_t>(tr, std::max<int64_t>(0, d[i].m - (int64_t)t * tr));
-            order.push_back({rows * d[i].n, make_int2(i, t)});
+            order.push_back({{cls, rows * d[i].n}, make_int2(i, t)});
         }
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<int64_t, int2>& a, const std::pair<int64_t, int2>& b) { return a.first > b.first; });
+    std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) {
+        return a.first.first != b.first.first ? a.first.first < b.first.first : a.first.second > b.first.second;
+    });
     p->tiles.reserve(order.size());
-    for (auto& o : order) p->tiles.push_back(o.second);
+    for (auto& o : order) {
+        p->tiles.push_back(o.second);
+        p->tile_end[o.first.first] = (int64_t)p->tiles.size();
+    }
+    for (int c = 1; c < kBatchClasses; ++c) p->tile_end[c] = std::max(p->tile_end[c], p->tile_end[c - 1]);
     for (auto& lv : levels) {
-        p->groups.insert(p->groups.end(), lv.begin(), lv.end());
-        p->level_end.push_back((int64_t)p->groups.size());
+        std::array<int64_t, kBatchClasses> ends{};
+        for (int c = 0; c < kBatchClasses; ++c) {
+            p->groups.insert(p->groups.end(), lv[c].begin(), lv[c].end());
+            ends[c] = (int64_t)p->groups.size();
+        }
+        p->level_end.push_back(ends);
     }
     p->slot_doubles = slots;
     p->off_tiles = align_up(p->mats.size() * sizeof(BatchMat), 256);
@@ -149,7 +172,6 @@ int batch_plan_create(const qless_matrix_desc* d, int32_t count, int64_t tile_by
     p->bytes = p->off_slots + align_up((size_t)std::max<int64_t>(slots, 1) * sizeof(double), 256);
     const DeviceInfo& di = current_device_info();
     p->waves_cap = di.num_cus * waves_per_cu;
-    p->nwaves = std::min<int64_t>((int64_t)p->tiles.size(), (int64_t)p->waves_cap);
     *out = p;
     return QLESS_OK;
 }
@@ -170,23 +192,35 @@ int batch_plan_upload(const qless_batch_plan* p, void* work, size_t work_bytes, 
 }
 
 int batch_run(const qless_batch_plan* p, void* work, size_t work_bytes, hipStream_t s) {
+    using batch_detail::kBatchClasses;
     if (p == nullptr) return QLESS_ERR_ARG;
     if (work == nullptr || (reinterpret_cast<uintptr_t>(work) & 255u) || work_bytes < p->bytes)
         return QLESS_ERR_WORKSPACE;
     char* b = static_cast<char*>(work);
     const BatchMat* mats = reinterpret_cast<const BatchMat*>(b);
     double* slots = reinterpret_cast<double*>(b + p->off_slots);
-    const int r_doubles = p->np_max * (p->np_max + 1) / 2 + p->np_max;
-    if (launch_batched_stage(mats, reinterpret_cast<const int2*>(b + p->off_tiles), (int64_t)p->tiles.size(),
-                             p->nwaves, slots, r_doubles, p->has_staged, s) != hipSuccess)
-        return QLESS_ERR_HIP;
+    const int2* tiles = reinterpret_cast<const int2*>(b + p->off_tiles);
     const BatchGroup* groups = reinterpret_cast<const BatchGroup*>(b + p->off_groups);
+    auto region = [&](int c) { return p->np_max[c] * (p->np_max[c] + 1) / 2 + p->np_max[c]; };
+    // stage 1: one persistent launch per width class present
     int64_t lo = 0;
-    for (int64_t hi : p->level_end) {
-        const int64_t ng = hi - lo;
-        const int64_t nw = std::min<int64_t>(ng, (int64_t)p->waves_cap);
-        if (launch_batched_tree(mats, groups + lo, ng, nw, slots, r_doubles, s) != hipSuccess) return QLESS_ERR_HIP;
-        lo = hi;
+    for (int c = 0; c < kBatchClasses; ++c) {
+        const int64_t nt = p->tile_end[c] - lo;
+        if (nt > 0 && launch_batched_stage(c, mats, tiles + lo, nt, std::min<int64_t>(nt, p->waves_cap), slots,
+                                           region(c), c == 0, s) != hipSuccess)
+            return QLESS_ERR_HIP;
+        lo = p->tile_end[c];
+    }
+    // tree levels, each class's groups of a level in one launch
+    int64_t g0 = 0;
+    for (const auto& ends : p->level_end) {
+        for (int c = 0; c < kBatchClasses; ++c) {
+            const int64_t ng = ends[c] - g0;
+            if (ng > 0 && launch_batched_tree(c, mats, groups + g0, ng, std::min<int64_t>(ng, p->waves_cap), slots,
+                                              region(c), s) != hipSuccess)
+                return QLESS_ERR_HIP;
+            g0 = ends[c];
+        }
     }
     return QLESS_OK;
 }

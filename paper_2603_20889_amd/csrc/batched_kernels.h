@@ -19,20 +19,35 @@ constexpr int kStageDoubles = 2048;
 constexpr int kStageOffset = 64;
 
 // Padded widths of the batched kernels and their rows per lane (the
-// single-matrix defaults of those widths).
-#define QLESS_BATCH_SWITCH(np, CALL)  \
-    switch (np) {                     \
-        case 1: CALL(1, 32); break;   \
-        case 2: CALL(2, 16); break;   \
-        case 4: CALL(4, 8); break;    \
-        case 8: CALL(8, 4); break;    \
-        case 16: CALL(16, 4); break;  \
-        case 24: CALL(24, 21); break; \
-        case 32: CALL(32, 16); break; \
-        case 40: CALL(40, 12); break; \
-        case 48: CALL(48, 10); break; \
-        case 56: CALL(56, 8); break;  \
-        default: CALL(64, 7); break;  \
+// single-matrix defaults of those widths), in four classes compiled as four
+// kernels: one kernel holding every width would take the registers of the
+// widest (and spill), starving the narrow ones of occupancy.
+//   class 0: n <= 8 (lane-private folds, LDS-staged panels)
+//   class 1: n = 9..16 (cross-lane fold)
+//   class 2: n = 17..32, class 3: n = 33..64 (column-group fold)
+constexpr int kBatchClasses = 4;
+
+constexpr int batch_class(int np) { return np <= 8 ? 0 : np <= 16 ? 1 : np <= 32 ? 2 : 3; }
+
+#define QLESS_BATCH_SWITCH_0(np, CALL) \
+    switch (np) {                      \
+        case 1: CALL(1, 32); break;    \
+        case 2: CALL(2, 16); break;    \
+        case 4: CALL(4, 8); break;     \
+        default: CALL(8, 4); break;    \
+    }
+#define QLESS_BATCH_SWITCH_1(np, CALL) { CALL(16, 4); }
+#define QLESS_BATCH_SWITCH_2(np, CALL) \
+    switch (np) {                      \
+        case 24: CALL(24, 21); break;  \
+        default: CALL(32, 16); break;  \
+    }
+#define QLESS_BATCH_SWITCH_3(np, CALL) \
+    switch (np) {                      \
+        case 40: CALL(40, 12); break;  \
+        case 48: CALL(48, 10); break;  \
+        case 56: CALL(56, 8); break;   \
+        default: CALL(64, 7); break;   \
     }
 
 // Fold tile t of matrix M (rows [t*tile_rows, ...)) and write its triangle to

@@ -7,6 +7,7 @@
 namespace qless {
 namespace batch_detail {
 
+template <int CLS>
 __global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
 batched_stage_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__ tiles, int64_t ntiles,
                      int64_t nwaves, double* __restrict__ slots, int region_doubles, int staged) {
@@ -21,21 +22,32 @@ batched_stage_kernel(const BatchMat* __restrict__ mats, const int2* __restrict__
         const int2 tl = tiles[t];
         const BatchMat M = mats[tl.x];
 #define QLESS_STAGE_CALL(NP, RPL) batch_stage_tile<NP, RPL>(M, tl.y, Rw, slots, stage, lane)
-        QLESS_BATCH_SWITCH(M.np, QLESS_STAGE_CALL)
+        if constexpr (CLS == 0) QLESS_BATCH_SWITCH_0(M.np, QLESS_STAGE_CALL)
+        else if constexpr (CLS == 1) QLESS_BATCH_SWITCH_1(M.np, QLESS_STAGE_CALL)
+        else if constexpr (CLS == 2) QLESS_BATCH_SWITCH_2(M.np, QLESS_STAGE_CALL)
+        else QLESS_BATCH_SWITCH_3(M.np, QLESS_STAGE_CALL)
 #undef QLESS_STAGE_CALL
     }
 }
 
 }  // namespace batch_detail
 
-hipError_t launch_batched_stage(const BatchMat* mats, const int2* tiles, int64_t ntiles, int64_t nwaves,
+// Stage 1 over the tiles [0, ntiles) of one width class (all of the same
+// class, longest first).
+hipError_t launch_batched_stage(int cls, const BatchMat* mats, const int2* tiles, int64_t ntiles, int64_t nwaves,
                                 double* slots, int r_doubles, bool staged, hipStream_t s) {
     using namespace batch_detail;
     int region = r_doubles;
     if (staged && region < kStageOffset + kStageDoubles) region = kStageOffset + kStageDoubles;
     const size_t lds = (size_t)kBatchWpb * region * sizeof(double);
-    hipLaunchKernelGGL(batched_stage_kernel, dim3((unsigned)ceil_div(nwaves, kBatchWpb)), dim3(64 * kBatchWpb), lds,
-                       s, mats, tiles, ntiles, nwaves, slots, region, staged ? 1 : 0);
+    const dim3 grid((unsigned)ceil_div(nwaves, kBatchWpb)), block(64 * kBatchWpb);
+    const int st = staged ? 1 : 0;
+    switch (cls) {
+        case 0: hipLaunchKernelGGL(batched_stage_kernel<0>, grid, block, lds, s, mats, tiles, ntiles, nwaves, slots, region, st); break;
+        case 1: hipLaunchKernelGGL(batched_stage_kernel<1>, grid, block, lds, s, mats, tiles, ntiles, nwaves, slots, region, st); break;
+        case 2: hipLaunchKernelGGL(batched_stage_kernel<2>, grid, block, lds, s, mats, tiles, ntiles, nwaves, slots, region, st); break;
+        default: hipLaunchKernelGGL(batched_stage_kernel<3>, grid, block, lds, s, mats, tiles, ntiles, nwaves, slots, region, st); break;
+    }
     return hipGetLastError();
 }
 

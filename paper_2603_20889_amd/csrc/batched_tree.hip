@@ -5,6 +5,7 @@
 namespace qless {
 namespace batch_detail {
 
+template <int CLS>
 __global__ void __launch_bounds__(64 * kBatchWpb) __attribute__((amdgpu_waves_per_eu(2)))
 batched_tree_kernel(const BatchMat* __restrict__ mats, const BatchGroup* __restrict__ groups, int64_t ngroups,
                     int64_t nwaves, double* __restrict__ slots, int r_doubles) {
@@ -18,19 +19,28 @@ batched_tree_kernel(const BatchMat* __restrict__ mats, const BatchGroup* __restr
         const BatchGroup G = groups[q];
         const BatchMat M = mats[G.mat];
 #define QLESS_TREE_CALL(NP, RPL) batch_tree_group<NP, RPL>(M, G, Rw, slots, lane)
-        QLESS_BATCH_SWITCH(M.np, QLESS_TREE_CALL)
+        if constexpr (CLS == 0) QLESS_BATCH_SWITCH_0(M.np, QLESS_TREE_CALL)
+        else if constexpr (CLS == 1) QLESS_BATCH_SWITCH_1(M.np, QLESS_TREE_CALL)
+        else if constexpr (CLS == 2) QLESS_BATCH_SWITCH_2(M.np, QLESS_TREE_CALL)
+        else QLESS_BATCH_SWITCH_3(M.np, QLESS_TREE_CALL)
 #undef QLESS_TREE_CALL
     }
 }
 
 }  // namespace batch_detail
 
-hipError_t launch_batched_tree(const BatchMat* mats, const BatchGroup* groups, int64_t ngroups, int64_t nwaves,
-                               double* slots, int r_doubles, hipStream_t s) {
+// One tree level of one width class: its groups [0, ngroups).
+hipError_t launch_batched_tree(int cls, const BatchMat* mats, const BatchGroup* groups, int64_t ngroups,
+                               int64_t nwaves, double* slots, int r_doubles, hipStream_t s) {
     using namespace batch_detail;
     const size_t lds = (size_t)kBatchWpb * r_doubles * sizeof(double);
-    hipLaunchKernelGGL(batched_tree_kernel, dim3((unsigned)ceil_div(nwaves, kBatchWpb)), dim3(64 * kBatchWpb), lds, s,
-                       mats, groups, ngroups, nwaves, slots, r_doubles);
+    const dim3 grid((unsigned)ceil_div(nwaves, kBatchWpb)), block(64 * kBatchWpb);
+    switch (cls) {
+        case 0: hipLaunchKernelGGL(batched_tree_kernel<0>, grid, block, lds, s, mats, groups, ngroups, nwaves, slots, r_doubles); break;
+        case 1: hipLaunchKernelGGL(batched_tree_kernel<1>, grid, block, lds, s, mats, groups, ngroups, nwaves, slots, r_doubles); break;
+        case 2: hipLaunchKernelGGL(batched_tree_kernel<2>, grid, block, lds, s, mats, groups, ngroups, nwaves, slots, r_doubles); break;
+        default: hipLaunchKernelGGL(batched_tree_kernel<3>, grid, block, lds, s, mats, groups, ngroups, nwaves, slots, r_doubles); break;
+    }
     return hipGetLastError();
 }
 

@@ -478,22 +478,28 @@ apply_mfma_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, i
 }
 
 // n <= 8, row layout: each lane holds RPL full rows of a 64*RPL-row panel (the
-// TSQR panel loads), forms y = x M (M from LDS, broadcast reads) and writes
-// its rows of Q; lanes write consecutive rows.
+// TSQR panel loads) and forms y = x M (M from LDS, broadcast reads).  Where
+// Q's rows are contiguous (ldq == n) a full panel of Q is one contiguous
+// block: the wavefront writes its rows into an LDS buffer and stores the
+// block with consecutive lanes on consecutive 16-byte pieces (each store
+// instruction covers 1 KB); otherwise each lane writes its own rows.
 template <int NP, int RPL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 apply_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_wave,
                   int64_t nwaves, const double* __restrict__ M, double* __restrict__ Q, int64_t ldq,
                   const int* __restrict__ fail) {
     constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    constexpr int BLOCK = (int)PANEL * NP;          // doubles of one full panel of Q
     __shared__ double Ms[NP * NP];
+    __shared__ __attribute__((aligned(16))) double qs[4][NP % 2 == 0 ? BLOCK : 2];
     for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
         const int k = e / NP, c = e % NP;
         Ms[e] = (k < n && c < n) ? M[(int64_t)k * n + c] : 0.0;
     }
     __syncthreads();
     const int lane = lane_id();
-    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wib;
     if (w >= nwaves) return;
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
@@ -502,8 +508,8 @@ apply_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, i
         return;
     }
     const bool fast = (n == NP) && (PANEL * ldx * 8 < 0x7FFFFFFF);
-    // 16-byte stores of column pairs when every row of Q starts 16-byte aligned
-    const bool vec_store = (n == NP) && (ldq % 2 == 0) && (reinterpret_cast<uintptr_t>(Q) % 16 == 0);
+    // contiguous, 16-byte aligned panels of Q: stored as blocks through LDS
+    const bool block_store = (n == NP) && (ldq == NP) && (reinterpret_cast<uintptr_t>(Q) % 16 == 0);
     for (int64_t base = r_begin; base < r_end; base += PANEL) {
         double x[RPL][NP];
         const bool full = base + PANEL <= r_end;
@@ -521,25 +527,30 @@ apply_rows_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, i
                 for (int i = 0; i < RPL; ++i) y[i][c] = fma(x[i][k], mkc, y[i][c]);
             }
         }
+        if constexpr (NP % 2 == 0) {
+            if (block_store && full) {
+                double* st = qs[wib];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+#pragma unroll
+                    for (int c = 0; c < NP; ++c) st[(lane + kWave * i) * NP + c] = y[i][c];
+                __builtin_amdgcn_wave_barrier();
+                f64x2* dst = reinterpret_cast<f64x2*>(Q + base * ldq);
+                const f64x2* src = reinterpret_cast<const f64x2*>(st);
+#pragma unroll
+                for (int f = lane; f < BLOCK / 2; f += kWave) __builtin_nontemporal_store(src[f], dst + f);
+                __builtin_amdgcn_wave_barrier();   // the next panel overwrites the buffer
+                continue;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int64_t row = base + lane + kWave * i;
             if (row < r_end) {
                 double* q = Q + row * ldq;
-                bool done = false;
-                if constexpr (NP % 2 == 0) {
-                    if (vec_store) {
 #pragma unroll
-                        for (int c = 0; c < NP; c += 2)
-                            __builtin_nontemporal_store(f64x2{y[i][c], y[i][c + 1]}, reinterpret_cast<f64x2*>(q + c));
-                        done = true;
-                    }
-                }
-                if (!done) {
-#pragma unroll
-                    for (int c = 0; c < NP; ++c)
-                        if (c < n) __builtin_nontemporal_store(y[i][c], &q[c]);
-                }
+                for (int c = 0; c < NP; ++c)
+                    if (c < n) __builtin_nontemporal_store(y[i][c], &q[c]);
             }
         }
     }

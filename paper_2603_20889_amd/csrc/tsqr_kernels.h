@@ -53,6 +53,21 @@ constexpr int tri_size() {
 }
 
 
+// A reflector is applied only where alpha^2 + s is at least this (2^-1000,
+// about 9e-302); below it the column is left as it is.  Inputs in the
+// documented range (|x| >= 1e-150) never come near it; what does is the
+// roundoff residue of a block with fewer rows than columns, which shrinks by
+// a factor of about u per column (a one-row block at n = 21 reaches 1e-300
+// by its last columns), and whose square would pass a subnormal to the
+// reciprocal square-root estimate (flushed to zero there: inf, then NaN).
+// Leaving such a residue in the panel changes R by far less than one unit
+// in the last place of any entry.
+constexpr double kTinySq = 0x1p-1000;
+
+__device__ __forceinline__ bool reflector_needed(double alpha, double s) {
+    return s != 0.0 && fma(alpha, alpha, s) >= kTinySq;
+}
+
 // Scalars of the reflector that maps (alpha, x) with |x|^2 = s > 0 to
 // (beta, 0): nrm = sqrt(alpha^2 + s), beta = -sign(alpha) nrm (sign(+0) = +),
 // u0 = alpha - beta (its pivot entry) and gamma = 2 / (u^T u) =
@@ -137,13 +152,14 @@ struct FoldStep {
             const int v = org.template get<K>();
             const double r = Rw[tri_row<W>(J) + v];
             const double s = readlane_f64(p[0], red_locate(K, 0));
+            const bool apply = reflector_needed(alpha, s);
             if constexpr (REC) {
-                if (s == 0.0 && lane == 0) {
+                if (!apply && lane == 0) {
                     rec[J] = 0.0;
                     rec[NP + J] = 0.0;
                 }
             }
-            if (s != 0.0) {
+            if (apply) {
                 double beta, u0, gamma;
                 reflector_scalars(alpha, s, beta, u0, gamma);
                 if constexpr (REC) {
@@ -190,7 +206,7 @@ struct LaneFoldStep {
             const double alpha = Rl[r0];
             double beta, u0, gamma;
             reflector_scalars(alpha, s, beta, u0, gamma);
-            const bool nz = s != 0.0;          // a zero column is left as it is
+            const bool nz = reflector_needed(alpha, s);   // a zero column is left as it is
             gamma = nz ? gamma : 0.0;
             u0 = nz ? u0 : 0.0;
             Rl[r0] = nz ? beta : alpha;
@@ -557,7 +573,7 @@ struct FoldStep2D {
             for (int a = 0; a < A; ++a) p[a] = sum_over_row_groups(p[a]);
             const double s = readlane_f64(p[0], cgJ);   // |panel part of column J|^2
             const double alpha = Rw[tri_row<NP>(J)];
-            if (s != 0.0) {
+            if (reflector_needed(alpha, s)) {
                 double beta, u0, gamma;
                 reflector_scalars(alpha, s, beta, u0, gamma);
 #pragma unroll

@@ -43,15 +43,16 @@ __device__ __forceinline__ const double* cat_col(const CatSrc& s, int c, int64_t
 template <int NP, int RPL>
 __device__ __forceinline__ void load_cat_1d(double (&x)[RPL][NP], const CatSrc& s, int64_t base, int64_t r_end,
                                             int lane) {
+    const double* col[NP];
+    int64_t ld[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) {
-        int64_t ld;
-        const double* col = cat_col(s, c, ld);   // wave-uniform
+    for (int c = 0; c < NP; ++c) col[c] = cat_col(s, c, ld[c]);   // wave-uniform
+    // a row's columns back to back, so that each cache line is fetched once
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int64_t row = base + lane + (int64_t)kWave * i;
-            x[i][c] = (col != nullptr && row < r_end) ? col[row * ld] : 0.0;
-        }
+    for (int i = 0; i < RPL; ++i) {
+        const int64_t row = base + lane + (int64_t)kWave * i;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) x[i][c] = (col[c] != nullptr && row < r_end) ? col[c][row * ld[c]] : 0.0;
     }
 }
 
@@ -60,16 +61,17 @@ __device__ __forceinline__ void load_cat_1d(double (&x)[RPL][NP], const CatSrc& 
 template <int NP, int RPL>
 __device__ __forceinline__ void load_cat_2d(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
                                             int64_t r_end, int lane) {
+    constexpr int NC = NP / kG2;
     const int rg = lane / kG2, cg = lane % kG2;
+    const double* col[NC];
+    int64_t ld[NC];
 #pragma unroll
-    for (int u = 0; u < NP / kG2; ++u) {
-        int64_t ld;
-        const double* col = cat_col(s, cg + kG2 * u, ld);
+    for (int u = 0; u < NC; ++u) col[u] = cat_col(s, cg + kG2 * u, ld[u]);
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int64_t row = base + rg + (int64_t)kRG2 * i;
-            x[i][u] = (col != nullptr && row < r_end) ? col[row * ld] : 0.0;
-        }
+    for (int i = 0; i < RPL; ++i) {
+        const int64_t row = base + rg + (int64_t)kRG2 * i;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) x[i][u] = (col[u] != nullptr && row < r_end) ? col[u][row * ld[u]] : 0.0;
     }
 }
 

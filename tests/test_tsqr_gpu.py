@@ -329,3 +329,26 @@ def test_running_state_matches_oracle(gpu, m_total, n, chunks):
     torch.cuda.synchronize(gpu)
     if m_total:
         check(X, R2.cpu().numpy())
+
+
+# A stage-1 block with a single row (m = k * panel + 1 rows, so the last
+# wavefront gets one): its roundoff residue shrinks by about u per column and
+# reached the subnormal range by the last columns at n >= ~20, where the
+# reflector scalars used to turn into NaN.  Every width class, ragged ones
+# included, on Gaussian data and on a least-squares [A b] (b nearly in the
+# range of A, as in the served workload).
+@pytest.mark.parametrize("n", [16, 17, 20, 21, 24, 31, 32, 40, 47, 48, 56, 64])
+def test_one_row_block_stays_finite(gpu, n):
+    q.qless_tune_set(n, 0, 0, 0)
+    rpl = q.qless_tune_get(n)["rows_per_lane"]
+    panel = (64 if n <= 16 else 8) * rpl
+    m = 150 * panel + 1
+    print("case one-row block n=%d m=%d" % (n, m), flush=True)
+    X = wl.gaussian(m, n, seed=31 + n)
+    check(X, run(X, gpu))
+    Ab, _ = wl.ls_request_data(m, n - 1, seed=77 + n)
+    R = run(Ab, gpu)
+    assert np.all(np.isfinite(R))
+    Ro = oracle.householder_r(Ab)
+    assert oracle.rel_err_r(R, Ro) <= E_R
+    assert oracle.row_scaled_err(R, Ro, 1e-4 * oracle.col_norm_max(Ab)) <= E_ROW
