@@ -11,8 +11,10 @@
 //
 // Layout: a workgroup of 256 threads stages a chunk of rows of X in LDS; thread
 // t owns a T x T tile of C (T = n/16 rounded up for n > 16, else 1), so that
-// 256 tiles cover the padded n x n matrix; per staged row it reads its 2T
-// operands from LDS and updates T^2 double-double accumulators.  Every
+// the tiles cover the padded n x n matrix -- for n <= 16 the 256 threads form
+// 256 / n^2 groups, each over every so many staged rows, whose tiles are
+// added at the end; per staged row a thread reads its 2T operands from LDS
+// and updates T^2 double-double accumulators.  Every
 // workgroup writes its partial (hi, lo) to the workspace and a fixed-order
 // double-double sum follows: no atomics, bitwise reproducible.
 //
@@ -123,17 +125,25 @@ constexpr int dd_grid() {   // tiles per dimension
 }
 
 template <int NP>
+constexpr int dd_groups() {   // thread groups sharing the staged rows (n <= 16: 256 / tiles)
+    return kDdThreads / (dd_grid<NP>() * dd_grid<NP>());
+}
+
+template <int NP>
 __global__ void __launch_bounds__(kDdThreads)
 gram_dd_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int64_t rows_per_block,
                double* __restrict__ part) {
     constexpr int T = dd_tile<NP>();
     constexpr int G = dd_grid<NP>();
+    constexpr int NG = dd_groups<NP>();              // thread groups, each over every NG-th staged row
     constexpr int LD = NP + 1;                       // odd row stride: operand reads spread over banks
     constexpr int CH = kDdStage / LD;                // rows per staged chunk
+    static_assert(NG * G * G == kDdThreads && NG * 2 * T * T <= kDdStage, "thread layout of the dd Gram kernel");
     __shared__ double xs[CH * LD];
     const int tid = threadIdx.x;
-    const int I = tid / G, J = tid % G;
-    const bool active = tid < G * G && I <= J;       // upper tiles only (C is symmetric)
+    const int tile = tid % (G * G), grp = tid / (G * G);
+    const int I = tile / G, J = tile % G;
+    const bool active = I <= J;                      // upper tiles only (C is symmetric)
     double hi[T][T], lo[T][T];
 #pragma unroll
     for (int a = 0; a < T; ++a)
@@ -150,7 +160,7 @@ gram_dd_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int6
         }
         __syncthreads();
         if (active) {
-            for (int r = 0; r < rows; ++r) {
+            for (int r = grp; r < rows; r += NG) {
                 double u[T], v[T];
 #pragma unroll
                 for (int a = 0; a < T; ++a) {
@@ -164,6 +174,23 @@ gram_dd_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int6
             }
         }
     }
+    // the groups' accumulators of a tile, added in group order (double-double)
+    dd acc[T][T];
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) acc[a][b] = dd_norm(hi[a][b], lo[a][b]);
+    if constexpr (NG > 1) {
+        __syncthreads();
+        xs[2 * tid] = acc[0][0].hi;
+        xs[2 * tid + 1] = acc[0][0].lo;
+        __syncthreads();
+        if (grp != 0) return;
+        for (int g = 1; g < NG; ++g) {
+            const int o = 2 * (g * G * G + tile);
+            acc[0][0] = dd_add(acc[0][0], dd{xs[o], xs[o + 1]});
+        }
+    }
     if (!active) return;
     // partial (hi, lo) of this block: 2 n x n matrices, both triangles
     double* ph = part + (int64_t)blockIdx.x * 2 * n * n;
@@ -174,11 +201,10 @@ gram_dd_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, int6
         for (int b = 0; b < T; ++b) {
             const int i = I * T + a, j = J * T + b;
             if (i < n && j < n) {
-                const dd v = dd_norm(hi[a][b], lo[a][b]);
-                ph[(int64_t)i * n + j] = v.hi;
-                pl[(int64_t)i * n + j] = v.lo;
-                ph[(int64_t)j * n + i] = v.hi;
-                pl[(int64_t)j * n + i] = v.lo;
+                ph[(int64_t)i * n + j] = acc[a][b].hi;
+                pl[(int64_t)i * n + j] = acc[a][b].lo;
+                ph[(int64_t)j * n + i] = acc[a][b].hi;
+                pl[(int64_t)j * n + i] = acc[a][b].lo;
             }
         }
 }
