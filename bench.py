@@ -394,6 +394,14 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads
             rec["tsqr_e_R_k%d" % k] = float(np.linalg.norm(Rs.cpu().numpy() - R0s) / nR0)
             rec["cholqr2_e_R_k%d" % k] = float(np.linalg.norm(Rc.cpu().numpy() - R0s) / nR0)
             rec["cholqr2_info_k%d" % k] = int(info.item())
+            if k == max(ks):
+                # the robust Gram variants at the worst conditioning of the sweep
+                for name, fn in (("shifted_cholqr3", q.shifted_cholqr3_r), ("cholqr2_dd", q.cholqr2_dd_r)):
+                    Rv, iv = fn(Xs)
+                    torch.cuda.synchronize()
+                    rec["%s_e_R_k%d" % (name, k)] = float(np.linalg.norm(Rv.cpu().numpy() - R0s) / nR0)
+                    rec["%s_info_k%d" % (name, k)] = int(iv.item())
+                    del Rv, iv
             if k == 4:
                 steps = 20 if ns <= 16 else 5
                 flush = torch.ones(2 ** 27, dtype=torch.float64, device=dev) if ns <= 4 else None
