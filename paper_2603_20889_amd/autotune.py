@@ -88,13 +88,20 @@ def _time_tsqr(X, steps: int, flush=None) -> float:
     return t[len(t) // 2]
 
 
-def tune_tsqr(ns, device=None, m: int = 1 << 25, steps: int = 15, min_gain: float = 0.015, log=print) -> dict:
+def tune_tsqr(ns, device=None, m: int = 1 << 25, steps: int = 9, finalists: int = 3, rounds: int = 5,
+              min_gain: float = 0.015, log=print) -> dict:
     """Tune qless_tsqr_r for every n in ns on m x n matrices (default the
     column sweep's m = 2^25), timing whole calls (median of `steps`, the
-    cache flushed between calls for inputs below 1 GiB).  A configuration
-    replaces the library default only when it is at least `min_gain` faster
-    (run-to-run spread is about 1 %).  Returns {n: {"rows_per_lane",
-    "waves_per_cu", "fan_in", "ms", "GBps", "default_ms"}}."""
+    cache flushed between calls for inputs below 1 GiB).
+
+    Selection takes two stages, since the fastest of some sixty noisy
+    screening times is fast partly by luck: every configuration is screened
+    once, then the `finalists` fastest and the library default are timed
+    again in `rounds` interleaved rounds, and each is scored by the median of
+    its rounds.  A configuration replaces the default only when its score is
+    at least `min_gain` below the default's (run-to-run spread is about 1 %).
+    Returns {n: {"rows_per_lane", "waves_per_cu", "fan_in", "ms", "GBps",
+    "default_ms"}} with the confirmed scores."""
     import torch
 
     import workloads as wl
@@ -105,18 +112,31 @@ def tune_tsqr(ns, device=None, m: int = 1 << 25, steps: int = 15, min_gain: floa
         flush = torch.ones(FLUSH_BELOW // 8, dtype=torch.float64, device=device) if 8 * m * n < FLUSH_BELOW else None
         q.qless_tune_set(n, 0, 0, 0)
         d = q.qless_tune_get(n)
-        default_ms = _time_tsqr(X, steps, flush)
-        best = {"rows_per_lane": d["rows_per_lane"], "waves_per_cu": d["waves_per_cu"], "fan_in": 0,
-                "ms": default_ms}
+        default = (d["rows_per_lane"], 0, 0)          # (rows_per_lane, waves_per_cu, fan_in); 0: library default
+        screened = []
         for rpl, wpc, fan in itertools.product(rows_per_lane_variants(n), WAVES_PER_CU, FAN_IN):
             q.qless_tune_set(n, wpc, fan, rpl)
-            ms = _time_tsqr(X, steps, flush)
-            if ms < best["ms"] * (1.0 - min_gain) or (ms < best["ms"] and best["ms"] < default_ms):
-                best = {"rows_per_lane": rpl, "waves_per_cu": wpc, "fan_in": fan, "ms": ms}
-        best.update({"GBps": 8.0 * m * n / (best["ms"] * 1e-3) / 1e9, "m": m, "default_ms": default_ms})
-        q.qless_tune_set(n, best["waves_per_cu"], best["fan_in"], best["rows_per_lane"])
-        table[n] = best
-        log("[autotune] n=%d -> %s" % (n, json.dumps(best)))
+            screened.append((_time_tsqr(X, steps, flush), (rpl, wpc, fan)))
+        screened.sort()
+        cands = [default] + [c for _, c in screened if c != default][:finalists]
+        times = {c: [] for c in cands}
+        for _ in range(rounds):
+            for c in cands:
+                q.qless_tune_set(n, c[1], c[2], c[0])
+                times[c].append(_time_tsqr(X, steps, flush))
+        score = {c: sorted(t)[len(t) // 2] for c, t in times.items()}
+        best = min(cands[1:], key=lambda c: score[c]) if len(cands) > 1 else default
+        if score[best] > score[default] * (1.0 - min_gain):
+            best = default
+        rpl, wpc, fan = best
+        if best == default:
+            wpc, fan = d["waves_per_cu"], 0
+        out = {"rows_per_lane": rpl, "waves_per_cu": wpc, "fan_in": fan, "ms": score[best],
+               "GBps": 8.0 * m * n / (score[best] * 1e-3) / 1e9, "m": m, "default_ms": score[default],
+               "screened": len(screened)}
+        q.qless_tune_set(n, wpc if best != default else 0, fan, rpl if best != default else 0)
+        table[n] = out
+        log("[autotune] n=%d -> %s" % (n, json.dumps(out)))
         del X, flush
         torch.cuda.empty_cache()
     return table

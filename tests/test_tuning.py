@@ -75,3 +75,47 @@ def test_apply_and_cache_file(tmp_path, monkeypatch):
     assert q.qless_tune_get(8) == {"waves_per_cu": 12, "fan_in": 8, "rows_per_lane": 4}
     monkeypatch.setenv("QLESS_TUNE", "off")
     assert autotune.apply_cached(device="x", path=str(path)) is None
+
+
+def _fake_timer(monkeypatch, true_ms, lucky=None):
+    """Replace the GPU timing by a function of the configuration in effect:
+    true_ms(config) for every call, except that the configuration `lucky`
+    times 20 % fast on its first (screening) call only."""
+    seen = set()
+
+    def fake(X, steps, flush=None):
+        n = X.shape[1]
+        t = q.qless_tune_get(n)
+        c = (t["rows_per_lane"], t["waves_per_cu"], t["fan_in"])
+        ms = true_ms(c)
+        if c == lucky and c not in seen:
+            seen.add(c)
+            return 0.8 * ms
+        return ms
+
+    monkeypatch.setattr(autotune, "_time_tsqr", fake)
+
+
+def test_tuner_keeps_default_against_a_lucky_screen(monkeypatch):
+    """A configuration that is fast only on its screening call does not
+    survive the confirmation rounds."""
+    d = q.qless_tune_get(8)
+    lucky = (8, 16, 32)
+    _fake_timer(monkeypatch, lambda c: 1.0, lucky=lucky)
+    table = autotune.tune_tsqr([8], device="cpu", m=1024, log=lambda *a: None)
+    got = table[8]
+    assert (got["rows_per_lane"], got["waves_per_cu"], got["fan_in"]) == (d["rows_per_lane"], d["waves_per_cu"], 0)
+    assert got["ms"] == got["default_ms"] == 1.0
+
+
+def test_tuner_takes_a_confirmed_gain(monkeypatch):
+    """A configuration at least min_gain faster on every round is chosen; one
+    under the threshold is not."""
+    better = (8, 12, 16)
+    _fake_timer(monkeypatch, lambda c: 0.95 if c == better else 1.0)
+    got = autotune.tune_tsqr([8], device="cpu", m=1024, log=lambda *a: None)[8]
+    assert (got["rows_per_lane"], got["waves_per_cu"], got["fan_in"]) == better
+    assert q.qless_tune_get(8) == {"rows_per_lane": 8, "waves_per_cu": 12, "fan_in": 16}
+    _fake_timer(monkeypatch, lambda c: 0.99 if c == better else 1.0)
+    got = autotune.tune_tsqr([8], device="cpu", m=1024, log=lambda *a: None)[8]
+    assert (got["waves_per_cu"], got["fan_in"]) == (q.qless_tune_get(8)["waves_per_cu"], 0)
