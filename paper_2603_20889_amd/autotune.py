@@ -3,7 +3,8 @@
 For each column count n it times ``qless_tsqr_r`` on a synthetic m x n
 matrix over a small grid of
   * rows_per_lane  -- panel height (the compiled variants for that n; for
-                      n > 16, 1 selects the matrix-core blocked fold),
+                      n > 16, 1 selects the matrix-core blocked fold and
+                      12 / 16 / 24 the 4 x 16 column-group fold),
   * waves_per_cu   -- stage-1 row blocks per compute unit,
   * fan_in         -- triangles combined per tree wavefront,
 keeps the fastest, and stores the table in a JSON cache keyed by GPU
@@ -43,14 +44,19 @@ def _key(device) -> str:
     return "%s|%s" % (_arch(device), q.version())
 
 
+# Every rows-per-lane value some compiled instance uses (for n > 16, 1 is
+# the matrix-core blocked fold, 12 / 16 / 24 the 4 x 16 column-group fold of
+# n padding to 64 / 48 / 32, and the rest the 8 x 8 column-group fold).
+RPL_CANDIDATES = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16, 21, 24, 32, 64)
+
+
 def rows_per_lane_variants(n: int) -> list[int]:
     """Compiled panel heights for n (the default first)."""
     q.qless_tune_set(n, 0, 0, 0)
     default = q.qless_tune_get(n)["rows_per_lane"]
     out = [default]
-    # 1 for n > 16: the matrix-core blocked fold (64-row panels)
-    for cand in (default // 2, default * 2) + ((1,) if n > 16 else ()):
-        if cand >= 1 and cand not in out:
+    for cand in RPL_CANDIDATES:
+        if cand not in out:
             try:
                 q.qless_tune_set(n, 0, 0, cand)
                 out.append(cand)

@@ -237,7 +237,10 @@ struct TsqrPlan {
 };
 
 // tuned = false ignores the qless_tune_set overrides (the default instance).
-TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned = true);
+// rpl != 0 asks for the instance with that many rows per lane (it must
+// exist for the padded width; callers that pair the plan with a kernel of
+// their own, the two-phase fold, pass that kernel's).
+TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned = true, int rpl = 0);
 // The tree of a plan over k >= 2 stacked triangles in src (dst takes the
 // intermediate levels); writes R (ld ldr) with a non-negative diagonal.
 hipError_t launch_tsqr_tree(const TsqrPlan& plan, double* src, double* dst, int64_t k, int64_t n, double* R,

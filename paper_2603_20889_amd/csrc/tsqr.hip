@@ -13,9 +13,9 @@ namespace qless {
 #define QLESS_DECL(NP, RPL) hipError_t launch_fold_np##NP##_r##RPL(const FoldArgs& a, hipStream_t s);
 #define QLESS_INSTANCES(X)                                                                          \
     X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5)              \
-    X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)                     \
+    X(14, 4) X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 16) X(56, 8) X(64, 12)                    \
     X(1, 64) X(2, 32) X(3, 21) X(4, 16) X(5, 12) X(6, 10) X(7, 9) X(8, 8) X(16, 2) X(32, 8) X(64, 4)  \
-    X(16, 3) X(32, 1) X(48, 1) X(64, 1)
+    X(16, 3) X(32, 1) X(48, 1) X(64, 1) X(32, 24) X(48, 10) X(64, 7)
 QLESS_INSTANCES(QLESS_DECL)
 #undef QLESS_DECL
 // One-workgroup last tree level, compiled for n <= 16 (launch_tree_np<NP>_r<RPL>).
@@ -36,10 +36,14 @@ struct Instance {
     int rpl;
     FoldFn fn;
     TreeFn tree;   // one-workgroup last level (n <= 16), else null
+    int wpb;       // wavefronts per workgroup of the instance's fold kernel
+    int64_t panel; // rows of one panel (the unit rows_per_wave is rounded to)
 };
 
 const Instance kInstances[] = {
-#define QLESS_ENTRY(NP, RPL) {NP, RPL, launch_fold_np##NP##_r##RPL, nullptr},
+#define QLESS_ENTRY(NP, RPL)                                                                  \
+    {NP, RPL, launch_fold_np##NP##_r##RPL, nullptr, tsqr_detail::waves_per_block<NP, RPL>(), \
+     tsqr_detail::panel_rows<NP, RPL>()},
     QLESS_INSTANCES(QLESS_ENTRY)
 #undef QLESS_ENTRY
 };
@@ -55,32 +59,6 @@ const TreeEntry kTrees[] = {
     QLESS_TREE_INSTANCES(QLESS_TREE_ENTRY)
 #undef QLESS_TREE_ENTRY
 };
-
-// Matrix-core instance (tsqr_detail::mf_instance) and wavefronts per
-// workgroup of the fold kernel (tsqr_detail::waves_per_block).
-constexpr bool mf_instance_for(int np, int rpl) { return np > 16 && rpl == 1; }
-constexpr bool staged_instance_for(int np, int rpl) { return np <= 8 && rpl * np <= 40 && (rpl * np) % 2 == 0; }
-constexpr int waves_per_block_for(int np, int rpl) {
-    return staged_instance_for(np, rpl) ? tsqr_detail::kStagedWpb
-           : (mf_instance_for(np, rpl) || (np * (np + 1) / 2 + np) * 8 * 4 > 65536) ? 2 : 4;
-}
-static_assert(waves_per_block_for(8, 4) == tsqr_detail::waves_per_block<8, 4>() &&
-                  waves_per_block_for(1, 32) == tsqr_detail::waves_per_block<1, 32>() &&
-                  waves_per_block_for(1, 64) == tsqr_detail::waves_per_block<1, 64>() &&
-                  waves_per_block_for(7, 4) == tsqr_detail::waves_per_block<7, 4>() &&
-                  waves_per_block_for(16, 4) == tsqr_detail::waves_per_block<16, 4>() &&
-                  waves_per_block_for(56, 8) == tsqr_detail::waves_per_block<56, 8>() &&
-                  waves_per_block_for(64, 7) == tsqr_detail::waves_per_block<64, 7>() &&
-                  waves_per_block_for(32, 1) == tsqr_detail::waves_per_block<32, 1>(),
-              "host and device workgroup sizes differ");
-// Rows of one panel of an instance (the unit rows_per_wave is rounded to).
-constexpr int64_t panel_rows_for(int np, int rpl) {
-    return (int64_t)(np <= 16 || mf_instance_for(np, rpl) ? kWave : tsqr_detail::kRG2) * rpl;
-}
-static_assert(panel_rows_for(32, 1) == tsqr_detail::panel_rows<32, 1>() &&
-                  panel_rows_for(32, 16) == tsqr_detail::panel_rows<32, 16>() &&
-                  panel_rows_for(8, 4) == tsqr_detail::panel_rows<8, 4>(),
-              "host and device panel heights differ");
 
 TreeFn find_tree(int np, int rpl) {
     for (const TreeEntry& t : kTrees)
@@ -142,15 +120,18 @@ FoldFn find_fold(int npad, int rpl) {
     return (in && in->npad == npad && in->rpl == rpl) ? in->fn : nullptr;
 }
 
-int64_t tsqr_panel_rows(int npad, int rpl) { return panel_rows_for(npad, rpl); }
+int64_t tsqr_panel_rows(int npad, int rpl) {
+    const Instance* in = find_instance(npad, rpl);
+    return in ? in->panel : 0;
+}
 
-TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned) {
+TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned, int rpl) {
     TsqrPlan p;
     const Tuning t = (tuned && n >= 1 && n <= QLESS_MAX_N) ? g_tuning[n] : Tuning{};
-    const Instance* in = find_instance(npad_for(n), t.rpl);
+    const Instance* in = find_instance(npad_for(n), rpl ? rpl : t.rpl);
     p.npad = in->npad;
     p.rows_per_lane = in->rpl;
-    const int64_t panel = panel_rows_for(in->npad, in->rpl);
+    const int64_t panel = in->panel;
     const int64_t max_waves = (int64_t)(num_cus > 0 ? num_cus : 1) * (t.waves_per_cu ? t.waves_per_cu : 8);
     int64_t rpw = ceil_div(m > 0 ? m : 1, max_waves);
     rpw = ceil_div(rpw, panel) * panel;
@@ -159,7 +140,7 @@ TsqrPlan make_tsqr_plan(int64_t m, int64_t n, int num_cus, bool tuned) {
     if (m <= 4 * panel) rpw = ceil_div(m > 0 ? m : 1, panel) * panel;
     p.rows_per_wave = rpw;
     p.k0 = m > 0 ? ceil_div(m, rpw) : 1;
-    p.wpb = waves_per_block_for(in->npad, in->rpl);
+    p.wpb = in->wpb;
     // Each launch leaves one triangle per workgroup.  Tree for n <= 16:
     // fan-in levels of one panel per wavefront (fan_in = panel / n) until the
     // remaining triangles fit two panels per wavefront of the one-workgroup

@@ -187,6 +187,76 @@ struct FoldStep {
     }
 };
 
+// Step J of the fold (n <= 16) with the running R in registers instead of
+// LDS.  Lane l keeps in rr[J] the entry R_{J, J+v} of row J for the value v
+// that the transposed butterfly of step J leaves in it (every lane with the
+// same v holds the same entry), so a step touches no LDS: alpha = R_JJ is
+// read from a lane with v = 0, and the update coefficients of columns
+// J+1.. from lanes that finished them, by v_readlane into scalar registers
+// that the updates take as operands.  The arithmetic, and so the result, is
+// that of FoldStep; it serves the interior panels, where the next panel may
+// be streaming into LDS meanwhile.
+template <int NP, int RPL, int J, int K, int T>
+__device__ __forceinline__ void apply_coefs(double (&x)[RPL][NP], double coef) {
+    if constexpr (T < K) {
+        constexpr int src = red_locate(K, T);
+        const double c = readlane_f64(coef, src);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) x[i][J + T] = fma(-c, x[i][J], x[i][J + T]);
+        apply_coefs<NP, RPL, J, K, T + 1>(x, coef);
+    }
+}
+
+template <int NP, int RPL, int J>
+struct FoldStepReg {
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP], double (&rr)[NP], const LaneOrigins<NP>& org,
+                                               int lane) {
+        if constexpr (J < NP) {
+            constexpr int K = NP - J;
+            double p[K];
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) s = fma(x[i][J], x[i][J + t], s);
+                p[t] = s;
+            }
+            red_stages<K, 0>(p, lane);
+            constexpr int l0 = red_locate(K, 0);
+            const double s = readlane_f64(p[0], l0);
+            const double alpha = readlane_f64(rr[J], l0);
+            if (reflector_needed(alpha, s)) {
+                double beta, u0, gamma;
+                reflector_scalars(alpha, s, beta, u0, gamma);
+                const int v = org.template get<K>();
+                const double coef = gamma * fma(u0, rr[J], p[0]);   // gamma * (u^T column J+v)
+                rr[J] = (v == 0) ? beta : fma(-coef, u0, rr[J]);
+                apply_coefs<NP, RPL, J, K, 1>(x, coef);
+            }
+            FoldStepReg<NP, RPL, J + 1>::run(x, rr, org, lane);
+        }
+    }
+};
+
+// rr (the register form of FoldStepReg) from and to the packed triangle in LDS.
+template <int NP, int J = 0>
+__device__ __forceinline__ void load_rr(double (&rr)[NP], const double* __restrict__ Rw, const LaneOrigins<NP>& org) {
+    if constexpr (J < NP) {
+        rr[J] = Rw[tri_row<NP>(J) + org.template get<NP - J>()];
+        load_rr<NP, J + 1>(rr, Rw, org);
+    }
+}
+
+template <int NP, int J = 0>
+__device__ __forceinline__ void store_rr(const double (&rr)[NP], double* __restrict__ Rw, const LaneOrigins<NP>& org) {
+    if constexpr (J < NP) {
+        Rw[tri_row<NP>(J) + org.template get<NP - J>()] = rr[J];   // the holders of an entry write the same value
+        store_rr<NP, J + 1>(rr, Rw, org);
+    } else {
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Lane-private fold (n <= 8): lane l keeps its own running triangle Rl of
 // the rows it has loaded (packed, in registers) and folds its RPL rows of a
 // panel into it with no cross-lane traffic at all -- the reflector scalars
@@ -236,6 +306,13 @@ constexpr bool lane_private() {
 template <int NP, int RPL>
 constexpr bool mf_instance() {
     return NP > 16 && RPL == 1;
+}
+
+// Instances for n = 32, 48, 64 in the 4 x 16 column-group layout
+// (FoldStepG16): 4 row groups of 16 lanes, one DPP row each.
+template <int NP, int RPL>
+constexpr bool g16_instance() {
+    return (NP == 32 && RPL == 24) || (NP == 48 && RPL == 16) || (NP == 64 && RPL == 12);
 }
 
 
@@ -369,17 +446,38 @@ constexpr bool staged_instance() {
     return lane_private<NP>() && double_buffered<NP, RPL>() && (RPL * NP) % 2 == 0;
 }
 
+// The cross-lane fold of n = 10 and 16 streams its interior panels through
+// LDS the same way, with FoldStepReg, which leaves LDS to the loads.  (Measured
+// at m = 2^25 against the register-loaded panels: n = 10 5 % faster, n = 16
+// 1.5 %; n = 12 the same and n = 14 2.5 % slower, so those stay in registers.)
+template <int NP, int RPL>
+constexpr bool staged_xl_instance() {
+    return NP == 10 || NP == 16;
+}
+
+// Doubles of LDS staging per wavefront (one panel).
+template <int NP, int RPL>
+constexpr int stage_doubles() {
+    return (staged_instance<NP, RPL>() || staged_xl_instance<NP, RPL>()) ? kWave * RPL * NP : 0;
+}
+
 // Wavefronts per workgroup of the fold kernel: 8 for the LDS-staged
-// instances (n <= 8: one workgroup of 8 per CU holds eight 16-18 KB staging
-// buffers, and leaves half as many triangles for the tree as workgroups of
-// 4 would), 2 where four packed triangles would take more than 64 KB of LDS
-// and for the matrix-core instances (each wavefront also holds transposes in
-// LDS), else 4.
+// instances of n <= 8 (one workgroup of 8 per CU holds eight 16-18 KB
+// staging buffers, and leaves half as many triangles for the tree as
+// workgroups of 4 would); for the staged cross-lane instances as many (8, 4
+// or 2) as fit 150 KB of LDS with their one-panel buffers; 2 where four
+// packed triangles would take more than 64 KB of LDS and for the
+// matrix-core instances (each wavefront also holds transposes in LDS), else
+// 4.
 constexpr int kStagedWpb = 8;
 
 template <int NP, int RPL>
 constexpr int waves_per_block() {
     if constexpr (staged_instance<NP, RPL>()) return kStagedWpb;
+    if constexpr (staged_xl_instance<NP, RPL>()) {
+        constexpr long per = (long)(stage_doubles<NP, RPL>() + tri_size<NP>() + NP) * 8;
+        return 8 * per <= 150 * 1024 ? 8 : 4 * per <= 150 * 1024 ? 4 : 2;
+    }
     return (mf_instance<NP, RPL>() || (tri_size<NP>() + NP) * 8 * 4 > 65536) ? 2 : 4;
 }
 
@@ -389,26 +487,53 @@ __device__ __forceinline__ void wait_memory() {
 
 constexpr int kNontemporal = 2;   // buffer cache policy: nt
 
+// Staging layout.  A panel is copied in 16-byte chunks; with C = NP/2
+// chunks per row a power of two (n = 4, 8, 16), chunk g of the panel (row
+// g / C, chunk g % C of the row) is stored at chunk position
+// g ^ ((g >> 4) & (C - 1)) of the buffer: the XOR permutes chunks only within
+// an aligned 256-byte group, so each direct-to-LDS load still copies one
+// contiguous kilobyte of X, and it makes the 16 lanes of a 16-byte LDS read
+// (each reading the same chunk of its own row) meet 16 different bank
+// groups instead of 2 (n = 16) or 4 (n = 8).  Other widths keep the
+// linear layout.
+template <int NP>
+constexpr int stage_swizzle_chunks() {
+    return (NP == 4 || NP == 8 || NP == 16) ? NP / 2 : 0;
+}
+
 template <int NP, int RPL>
 __device__ __forceinline__ void stage_panel(const double* __restrict__ X, int64_t base, double* stage, int lane) {
     constexpr int NCHUNK = RPL * NP / 2;   // 1 KB chunks: 64 lanes x 16 bytes
+    constexpr int C = stage_swizzle_chunks<NP>();
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * NP), (short)0, 0x7FFFFFFF, 0x00020000);
+    // load j, lane l fills buffer chunk 64 j + l, which holds chunk
+    // 64 j + (l ^ z) of the panel, z = ((4 j + l / 16) & (C - 1)): it depends
+    // on j only through j & 1 (and not at all for C <= 4)
+    int vo[2] = {lane * 16, lane * 16};
+    if constexpr (C > 1) {
+        vo[0] = (lane ^ ((lane >> 4) & (C - 1))) * 16;
+        vo[1] = (lane ^ ((4 + (lane >> 4)) & (C - 1))) * 16;
+    }
 #pragma unroll
     for (int j = 0; j < NCHUNK; ++j)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(stage + j * 128), 16,
-                                                 lane * 16, j * 1024, 0, kNontemporal);
+                                                 vo[j & 1], j * 1024, 0, kNontemporal);
 }
 
 template <int NP, int RPL>
 __device__ __forceinline__ void read_staged_panel(double (&x)[RPL][NP], const double* stage, int lane) {
+    constexpr int C = stage_swizzle_chunks<NP>();
+    // chunk h of row r = lane + 64 i sits at chunk h ^ zl of the row's slot,
+    // zl = ((r C) >> 4) & (C - 1), the same for every i
+    const int zl = C > 1 ? ((lane * C) >> 4) & (C - 1) : 0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
         const double* row = stage + (lane + kWave * i) * NP;
 #pragma unroll
         for (int c = 0; c < NP; c += 2) {
             if constexpr (NP % 2 == 0) {
-                const f64x2 v = *reinterpret_cast<const f64x2*>(row + c);
+                const f64x2 v = *reinterpret_cast<const f64x2*>(row + 2 * ((c >> 1) ^ zl));
                 x[i][c] = v[0];
                 x[i][c + 1] = v[1];
             } else {
@@ -445,6 +570,25 @@ __device__ __forceinline__ void fold_panels_lane_private_staged(const double* __
     FoldStep<NP, NP, 0>::run(xe, Rw, Cw, org, lane);
 }
 
+// Staged cross-lane fold: interior panels of contiguous rows (ldx == n ==
+// NP) stream through the wavefront's LDS buffer as in the lane-private
+// staged fold, and are folded by FoldStepReg into rr.
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_panels_staged_reg(const double* __restrict__ X, int64_t base, int64_t nfull,
+                                                       double (&rr)[NP], const LaneOrigins<NP>& org, int lane,
+                                                       double* stage) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    stage_panel<NP, RPL>(X, base, stage, lane);
+    for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+        double x[RPL][NP];
+        wait_memory();                       // panel p is in LDS
+        read_staged_panel<NP, RPL>(x, stage, lane);
+        wait_memory();                       // and in registers: the buffer is free
+        if (p + 1 < nfull) stage_panel<NP, RPL>(X, base + PANEL, stage, lane);
+        FoldStepReg<NP, RPL, 0>::run(x, rr, org, lane);
+    }
+}
+
 // Fold rows [r_begin, r_end) of a row-major X (n columns, leading dimension
 // ldx) into the wavefront's R, panel by panel (layout for n <= 16).  Interior
 // panels come first: for n <= 8 and at least kLanePrivateMin of them, with
@@ -468,12 +612,15 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
     double* Cw = Rw + tri_size<NP>();   // per-wavefront coefficient exchange
     double xa[RPL][NP];
     int64_t base = r_begin;
-    if (n < NP && PANEL * ldx * 8 < 0x7FFFFFFF) {
+    if (n < NP && PANEL * ldx * 8 < 0x7FFFFFFF && base + PANEL <= r_end) {
         // padded width: interior panels one at a time, cross-lane fold
+        double rr[NP];
+        load_rr<NP>(rr, Rw, org);
         for (; base + PANEL <= r_end; base += PANEL) {
             load_panel_1d_padded<NP, RPL>(xa, X, n, ldx, base, lane);
-            FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
+            FoldStepReg<NP, RPL, 0>::run(xa, rr, org, lane);
         }
+        store_rr<NP>(rr, Rw, org);
     }
     if constexpr (lane_private<NP>()) {
         if (nfull >= kLanePrivateMin) {
@@ -490,26 +637,38 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
         }
     }
     if (nfull > 0) {
-        if constexpr (double_buffered<NP, RPL>()) {
-            double xb[RPL][NP];
-            const int64_t last = r_begin + (nfull - 1) * PANEL;
-            load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
-            while (true) {
-                load_panel_1d_fast<NP, RPL>(xb, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
-                FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
-                base += PANEL;
-                if (base > last) break;
-                load_panel_1d_fast<NP, RPL>(xa, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
-                FoldStep<NP, RPL, 0>::run(xb, Rw, Cw, org, lane);
-                base += PANEL;
-                if (base > last) break;
-            }
-        } else {
-            for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
-                load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
-                FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
+        double rr[NP];
+        load_rr<NP>(rr, Rw, org);
+        if constexpr (staged_xl_instance<NP, RPL>()) {
+            if (stage != nullptr && ldx == NP) {
+                fold_panels_staged_reg<NP, RPL>(X, base, nfull, rr, org, lane, stage);
+                base += nfull * PANEL;
+                nfull = 0;
             }
         }
+        if (nfull > 0) {
+            if constexpr (double_buffered<NP, RPL>()) {
+                double xb[RPL][NP];
+                const int64_t last = base + (nfull - 1) * PANEL;
+                load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
+                while (true) {
+                    load_panel_1d_fast<NP, RPL>(xb, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
+                    FoldStepReg<NP, RPL, 0>::run(xa, rr, org, lane);
+                    base += PANEL;
+                    if (base > last) break;
+                    load_panel_1d_fast<NP, RPL>(xa, X, ldx, base + PANEL < last ? base + PANEL : last, lane);
+                    FoldStepReg<NP, RPL, 0>::run(xb, rr, org, lane);
+                    base += PANEL;
+                    if (base > last) break;
+                }
+            } else {
+                for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+                    load_panel_1d_fast<NP, RPL>(xa, X, ldx, base, lane);
+                    FoldStepReg<NP, RPL, 0>::run(xa, rr, org, lane);
+                }
+            }
+        }
+        store_rr<NP>(rr, Rw, org);
     }
     for (; base < r_end; base += PANEL) {
         load_panel_1d_tail<NP, RPL>(xa, X, n, ldx, base, r_end, lane);
@@ -652,6 +811,142 @@ __device__ __forceinline__ void fold_rows_2d(const double* __restrict__ X, int n
         double x[RPL][NC];
         load_panel_2d<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
         FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4 x 16 column-group layout for n = 32, 48, 64.  Lane (rg, cg) = (l / 16,
+// l % 16) holds RPL rows (rg, rg+4, ...) of the panel and the columns
+// c = cg + 16u (u < NP/16).  A row group is one 16-lane DPP row, so the pivot
+// column of step J reaches the whole group with one v_mov_b64_dpp
+// row_newbcast per row, and the dot products are summed over the 4 row
+// groups by two v_permlane16/32_swap stages.  No LDS access in a step except
+// row J of R (read by every lane for its columns, written by row group 0),
+// and 64/4 = 16 rows per column slot and row group -- four times the rows
+// of the 8 x 8 layout -- to amortise the per-column sums and reflector
+// scalars.
+constexpr int kG4 = 16;                  // column groups (lanes per row group)
+constexpr int kRG4 = kWave / kG4;        // row groups
+
+template <int CG>
+__device__ __forceinline__ double bcast_row16(double v) {
+    // row_newbcast:CG (DPP control 0x150 + CG): lane CG of each 16-lane row to the row
+    const long r = __builtin_amdgcn_update_dpp(0L, __builtin_bit_cast(long, v), 0x150 + CG, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, r);
+}
+
+__device__ __forceinline__ double sum_over_row_groups4(double v) {
+    double a, b;
+    swap16_f64(v, a, b);   // lane ^ 16
+    v = a + b;
+    swap32_f64(v, a, b);   // lane ^ 32
+    return a + b;
+}
+
+template <int NP, int RPL, int J>
+struct FoldStepG16 {
+    static constexpr int NC = NP / kG4;
+    __device__ static __forceinline__ void run(double (&x)[RPL][NP / kG4], double* __restrict__ Rw, int lane) {
+        if constexpr (J < NP) {
+            constexpr int cgJ = J % kG4;
+            constexpr int uJ = J / kG4;
+            constexpr int A = NC - uJ;   // live column slots (slot uJ only partly live)
+            const int cg = lane % kG4;
+            double piv[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) piv[i] = bcast_row16<cgJ>(x[i][uJ]);
+            double p[A], r[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                const int c = cg + kG4 * (uJ + a);            // c <= J only in slot uJ: clamp
+                r[a] = Rw[tri_row<NP>(J) + (c > J ? c - J : 0)];
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) t = fma(piv[i], x[i][uJ + a], t);
+                p[a] = t;
+            }
+#pragma unroll
+            for (int a = 0; a < A; ++a) p[a] = sum_over_row_groups4(p[a]);
+            const double s = readlane_f64(p[0], cgJ);         // |panel part of column J|^2
+            const double alpha = readlane_f64(r[0], cgJ);     // R_JJ
+            if (reflector_needed(alpha, s)) {
+                double beta, u0, gamma;
+                reflector_scalars(alpha, s, beta, u0, gamma);
+                double nr[A];
+#pragma unroll
+                for (int a = 0; a < A; ++a) {
+                    const int c = cg + kG4 * (uJ + a);
+                    const bool live = (a > 0) || (c > J);
+                    const double coef = live ? gamma * fma(u0, r[a], p[a]) : 0.0;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) x[i][uJ + a] = fma(-coef, piv[i], x[i][uJ + a]);
+                    nr[a] = fma(-coef, u0, r[a]);
+                }
+                if (lane < kG4) {
+                    // the new row J of R; a column c <= J of slot uJ writes to the lane's spare slot
+#pragma unroll
+                    for (int a = 0; a < A; ++a) {
+                        const int c = cg + kG4 * (uJ + a);
+                        const bool live = (a > 0) || (c > J);
+                        Rw[live ? tri_row<NP>(J) + c - J : tri_size<NP>() + cg] = nr[a];
+                    }
+                    if (lane == 0) Rw[tri_row<NP>(J)] = beta;
+                }
+            }
+            FoldStepG16<NP, RPL, J + 1>::run(x, Rw, lane);
+        }
+    }
+};
+
+// Panel of 4 RPL rows at `base` in the 4 x 16 layout: lane (rg, cg) gets
+// rows base + rg + 4i, columns cg + 16u; rows >= r_end and columns >= n read
+// as zero.  Full panels load 16 consecutive doubles of a row per group.
+template <int NP, int RPL>
+__device__ __forceinline__ void load_panel_g16(double (&x)[RPL][NP / kG4], const double* __restrict__ X, int n,
+                                               int64_t ldx, int64_t base, int64_t r_end, bool fast, int lane) {
+    constexpr int NC = NP / kG4;
+    constexpr int64_t PANEL = (int64_t)kRG4 * RPL;
+    const int rg = lane / kG4, cg = lane % kG4;
+    if (fast && base + PANEL <= r_end) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + base * ldx), (short)0, 0x7FFFFFFF, 0x00020000);
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int c = cg + kG4 * u;
+            const bool ok = c < n;                     // a padded column reads column 0 (in bounds), zeroed
+            const int vo = (int)((rg * ldx + (ok ? c : 0)) * 8);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const double v = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, (int)(kRG4 * i * ldx * 8), 0));
+                x[i][u] = ok ? v : 0.0;
+            }
+        }
+    } else {
+        const int64_t left = r_end - base - rg;
+        const double* x0 = X + (left > 0 ? base + rg : 0) * ldx;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const bool ok = (int64_t)kRG4 * i < left;
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const int c = cg + kG4 * u;
+                x[i][u] = (ok && c < n) ? x0[(int64_t)kRG4 * i * ldx + c] : 0.0;
+            }
+        }
+    }
+}
+
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_rows_g16(const double* __restrict__ X, int n, int64_t ldx, int64_t r_begin,
+                                              int64_t r_end, double* __restrict__ Rw, int lane) {
+    constexpr int64_t PANEL = (int64_t)kRG4 * RPL;
+    if (r_begin >= r_end) return;
+    const bool fast = PANEL * ldx * 8 < 0x7FFFFFFF;
+    for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        double x[RPL][NP / kG4];
+        load_panel_g16<NP, RPL>(x, X, n, ldx, base, r_end, fast, lane);
+        FoldStepG16<NP, RPL, 0>::run(x, Rw, lane);
     }
 }
 
@@ -837,6 +1132,7 @@ __device__ __forceinline__ void fold_rows(const double* __restrict__ X, int n, i
                                           int64_t r_end, double* __restrict__ Rw, int lane,
                                           double* stage = nullptr) {
     if constexpr (mf_instance<NP, RPL>()) fold_rows_mfma<NP>(X, n, ldx, r_begin, r_end, Rw, stage, lane);
+    else if constexpr (g16_instance<NP, RPL>()) fold_rows_g16<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
     else if constexpr (NP <= 16) fold_rows_1d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane, stage);
     else fold_rows_2d<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane);
 }
@@ -844,7 +1140,7 @@ __device__ __forceinline__ void fold_rows(const double* __restrict__ X, int n, i
 // Rows of a panel for an instance (the unit rows_per_wave is rounded to).
 template <int NP, int RPL>
 constexpr int64_t panel_rows() {
-    return (int64_t)(NP <= 16 || mf_instance<NP, RPL>() ? kWave : kRG2) * RPL;
+    return (int64_t)(NP <= 16 || mf_instance<NP, RPL>() ? kWave : g16_instance<NP, RPL>() ? kRG4 : kRG2) * RPL;
 }
 
 template <int NP>
@@ -910,7 +1206,8 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
             FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
         }
     } else {
-        constexpr int CR = mf_instance<NP, RPL>() ? 4 : RPL;   // matrix-core instances combine in this layout
+        // the matrix-core and 4 x 16 instances combine in the 8 x 8 layout with 4 rows per lane
+        constexpr int CR = (mf_instance<NP, RPL>() || g16_instance<NP, RPL>()) ? 4 : RPL;
         const int rg = lane / kG2, cg = lane % kG2;
         for (int base = 0; base < rows; base += kRG2 * CR) {
             double x[CR][NP / kG2];
@@ -948,7 +1245,7 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
                  const double* Yinit) {
     constexpr int WPB = waves_per_block<NP, RPL>();
     constexpr int STRIDE = tri_size<NP>() + NP;
-    constexpr int STAGE = mf_instance<NP, RPL>() ? kMfScratch : staged_instance<NP, RPL>() ? kWave * RPL * NP : 2;
+    constexpr int STAGE = mf_instance<NP, RPL>() ? kMfScratch : stage_doubles<NP, RPL>() > 0 ? stage_doubles<NP, RPL>() : 2;
     static_assert((size_t)WPB * (STRIDE + STAGE) * sizeof(double) + 16 <= 160 * 1024,
                   "a workgroup must fit the 160 KB of LDS of a gfx950 compute unit");
     __shared__ double Rsh[WPB][STRIDE];
@@ -968,7 +1265,7 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     const int64_t r_begin = w * rows_per_wave;
     const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
     fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane,
-                       (mf_instance<NP, RPL>() || staged_instance<NP, RPL>()) ? stage[wib] : nullptr);
+                       (mf_instance<NP, RPL>() || stage_doubles<NP, RPL>() > 0) ? stage[wib] : nullptr);
     if (nvalid > 1) {
         int old = 0;
         if (lane == 0) old = __hip_atomic_fetch_add(&arrivals, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);

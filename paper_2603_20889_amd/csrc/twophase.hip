@@ -5,28 +5,46 @@
 
 namespace qless {
 
-#define QLESS_CAT_DECL(NP)                                                                                \
-    hipError_t launch_cat_np##NP(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out, \
-                                 int64_t ldo, int64_t ostride, int normalise, hipStream_t st);
-QLESS_CAT_DECL(1) QLESS_CAT_DECL(2) QLESS_CAT_DECL(3) QLESS_CAT_DECL(4) QLESS_CAT_DECL(5) QLESS_CAT_DECL(6)
-QLESS_CAT_DECL(7) QLESS_CAT_DECL(8) QLESS_CAT_DECL(10) QLESS_CAT_DECL(12) QLESS_CAT_DECL(14) QLESS_CAT_DECL(16)
-QLESS_CAT_DECL(24) QLESS_CAT_DECL(32) QLESS_CAT_DECL(40) QLESS_CAT_DECL(48) QLESS_CAT_DECL(56) QLESS_CAT_DECL(64)
+// Kernel instances (twophase_i*.hip): launch_cat_np<NP>_r<RPL>.  The TSQR
+// plan of a call is made for the same (NP, RPL), so that its rows per
+// wavefront, workgroup size and tree match what the kernel writes.
+#define QLESS_CAT_INSTANCES(X)                                                                   \
+    X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5) X(14, 4) \
+    X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)
+#define QLESS_CAT_DECL(NP, RPL)                                                                         \
+    hipError_t launch_cat_np##NP##_r##RPL(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, \
+                                          double* out, int64_t ldo, int64_t ostride, int normalise, hipStream_t st);
+QLESS_CAT_INSTANCES(QLESS_CAT_DECL)
 #undef QLESS_CAT_DECL
 
 namespace {
 
-hipError_t launch_cat(int npad, const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out,
-                      int64_t ldo, int64_t ostride, int normalise, hipStream_t st) {
+// Rows per lane of the two-phase instance of a padded width (0: none).
+int cat_rpl(int npad) {
     switch (npad) {
-#define QLESS_CAT_CASE(NP) \
-    case NP: return launch_cat_np##NP(s, m, rpw, nw, out, ldo, ostride, normalise, st);
-        QLESS_CAT_CASE(1) QLESS_CAT_CASE(2) QLESS_CAT_CASE(3) QLESS_CAT_CASE(4) QLESS_CAT_CASE(5)
-        QLESS_CAT_CASE(6) QLESS_CAT_CASE(7) QLESS_CAT_CASE(8) QLESS_CAT_CASE(10) QLESS_CAT_CASE(12)
-        QLESS_CAT_CASE(14) QLESS_CAT_CASE(16) QLESS_CAT_CASE(24) QLESS_CAT_CASE(32) QLESS_CAT_CASE(40)
-        QLESS_CAT_CASE(48) QLESS_CAT_CASE(56) QLESS_CAT_CASE(64)
-#undef QLESS_CAT_CASE
-        default: return hipErrorInvalidValue;
+#define QLESS_CAT_RPL(NP, RPL) \
+    case NP: return RPL;
+        QLESS_CAT_INSTANCES(QLESS_CAT_RPL)
+#undef QLESS_CAT_RPL
+        default: return 0;
     }
+}
+
+hipError_t launch_cat(int npad, int rpl, const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw,
+                      double* out, int64_t ldo, int64_t ostride, int normalise, hipStream_t st) {
+#define QLESS_CAT_CASE(NP, RPL) \
+    if (npad == NP && rpl == RPL) return launch_cat_np##NP##_r##RPL(s, m, rpw, nw, out, ldo, ostride, normalise, st);
+    QLESS_CAT_INSTANCES(QLESS_CAT_CASE)
+#undef QLESS_CAT_CASE
+    return hipErrorInvalidValue;
+}
+
+// The plan of a two-phase call: the untuned TSQR plan of width w, made for
+// the two-phase instance of its padded width.
+TsqrPlan cat_plan(int64_t m, int64_t w) {
+    const int cus = current_device_info().num_cus;
+    const TsqrPlan p0 = make_tsqr_plan(m, w, cus, false);
+    return make_tsqr_plan(m, w, cus, false, cat_rpl(p0.npad));
 }
 
 // B (p x n, ld ldb) = rows 0..p-1, columns p.. of Rf; R (n x n, ld ldr) =
@@ -60,7 +78,7 @@ extern "C" {
 
 size_t qless_two_phase_workspace_bytes(int64_t m, int64_t p, int64_t n) {
     if (!two_phase_sizes_ok(m, p, n) || p + n > QLESS_MAX_N) return 0;
-    return two_phase_work(make_tsqr_plan(m, p + n, current_device_info().num_cus, false), p + n);
+    return two_phase_work(cat_plan(m, p + n), p + n);
 }
 
 int qless_two_phase_r(const double* Y, int64_t p, int64_t ldy, const double* X, int64_t m, int64_t n, int64_t ldx,
@@ -73,7 +91,7 @@ int qless_two_phase_r(const double* Y, int64_t p, int64_t ldy, const double* X, 
     if (p > 0 && (B == nullptr || ldb < n)) return QLESS_ERR_ARG;
     if (p > 0 && m > 0 && (Y == nullptr || ldy < p)) return QLESS_ERR_ARG;
     const int64_t w = p + n;
-    const TsqrPlan plan = make_tsqr_plan(m, w, current_device_info().num_cus, false);
+    const TsqrPlan plan = cat_plan(m, w);
     const size_t need = two_phase_work(plan, w);
     if (work == nullptr || (reinterpret_cast<uintptr_t>(work) & 255u) != 0 || work_bytes < need)
         return QLESS_ERR_WORKSPACE;
@@ -83,12 +101,12 @@ int qless_two_phase_r(const double* Y, int64_t p, int64_t ldy, const double* X, 
     hipError_t e;
     timing_begin(kTimeTsqrStage1, stream);
     if (plan.k1 == 1) {
-        e = launch_cat(plan.npad, s, m, plan.rows_per_wave, plan.k0, Rf, w, 0, 1, stream);
+        e = launch_cat(plan.npad, plan.rows_per_lane, s, m, plan.rows_per_wave, plan.k0, Rf, w, 0, 1, stream);
         timing_end(kTimeTsqrStage1, stream);
     } else {
         double* src = tree;
         double* dst = reinterpret_cast<double*>(reinterpret_cast<char*>(tree) + plan.ybytes_a);
-        e = launch_cat(plan.npad, s, m, plan.rows_per_wave, plan.k0, src, w, w * w, 0, stream);
+        e = launch_cat(plan.npad, plan.rows_per_lane, s, m, plan.rows_per_wave, plan.k0, src, w, w * w, 0, stream);
         timing_end(kTimeTsqrStage1, stream);
         if (e == hipSuccess) e = launch_tsqr_tree(plan, src, dst, plan.k1, w, Rf, w, stream);
     }

@@ -9,7 +9,7 @@ they must agree to 4 u |G| + 4 m u^2 (|X|^T |X|) entrywise; inputs are chosen
 so that many entries cancel (|G_ij| much smaller than (|X|^T |X|)_ij), where
 a plain FP64 sum would miss this bar by orders of magnitude (checked on the
 same data).  cholqr2_dd_r is compared with the Householder oracle: e_R <=
-1e-12 (row-scaled <= 5e-12) at kappa <= 1e4, and at kappa = 1e10 .. 1e13 it
+1e-12 (row-scaled <= 2e-11) at kappa <= 1e4, and at kappa = 1e10 .. 1e13 it
 completes where cholqr2_r breaks down, with a Gram residual <= 1e-13 and
 e_R <= 1e-12 against the oracle."""
 import numpy as np

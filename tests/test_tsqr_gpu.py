@@ -193,7 +193,8 @@ def test_config3_full_size_known_r(gpu, n):
 # buffering, the workgroup combine and the tree, against the oracle.
 INSTANCES = [(1, 32), (1, 64), (2, 16), (2, 32), (3, 12), (3, 21), (4, 8), (4, 16), (5, 6), (5, 12), (6, 6),
              (6, 10), (7, 4), (7, 9), (8, 4), (8, 8), (10, 6), (12, 5), (14, 4), (16, 4), (16, 2), (16, 3),
-             (24, 21), (32, 16), (32, 8), (40, 12), (48, 10), (56, 8), (64, 7), (64, 4)]
+             (24, 21), (32, 16), (32, 8), (40, 12), (48, 10), (56, 8), (64, 7), (64, 4),
+             (32, 24), (48, 16), (64, 12)]
 
 
 @pytest.mark.parametrize("n,rpl", INSTANCES)

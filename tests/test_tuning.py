@@ -45,10 +45,12 @@ def test_tuning_changes_the_plan():
 
 def test_variants_listed():
     assert autotune.rows_per_lane_variants(8) == [4, 8]
-    assert autotune.rows_per_lane_variants(16)[0] == 4
-    # n > 16: the column-group variants and the matrix-core fold (one row per lane)
-    assert autotune.rows_per_lane_variants(32) == [16, 8, 1]
-    assert autotune.rows_per_lane_variants(64) == [7, 1]
+    assert autotune.rows_per_lane_variants(16) == [4, 2, 3]
+    # n > 16: the 8 x 8 column-group variants, the matrix-core fold (one row
+    # per lane) and the 4 x 16 column-group fold (the default for 48 and 64)
+    assert autotune.rows_per_lane_variants(32) == [16, 1, 8, 24]
+    assert autotune.rows_per_lane_variants(48) == [16, 1, 10]
+    assert autotune.rows_per_lane_variants(64) == [12, 1, 4, 7]
     assert autotune.rows_per_lane_variants(24) == [21]
 
 

@@ -4,7 +4,7 @@ oracle, which forms B by pairwise sums, Z = X - Y B row by row and R(Z) by
 plain Householder.  The GPU runs one Q-less TSQR over [Y X] read from the two
 pointers.
 
-Bar: e_R(R, R_oracle) <= 1e-12 and the row-scaled error <= 5e-12 (as for
+Bar: e_R(R, R_oracle) <= 1e-12 and the row-scaled error <= 2e-11 (as for
 qless_tsqr_r, rows judged at kappa <= 1e4 relative to X's largest column,
 whose part in span(Y) makes it larger than R's) at kappa(R0) <= 1e4 on inputs X = Y B0 + W R0 with [Y W]
 orthonormal, where the projected part is not small against X; B within
