@@ -36,7 +36,7 @@ def check(Y, X, B, R):
     Bo, Ro = oracle.two_phase_r(Y, X)
     assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) >= 0.0)
     assert oracle.rel_err_r(R, Ro) <= E_R, oracle.rel_err_r(R, Ro)
-    assert oracle.row_scaled_err(R, Ro, 1e-4 * oracle.col_norm_max(X)) <= e_row(R.shape[0])
+    assert oracle.row_scaled_err(R, Ro, 1e-4 * oracle.col_norm_max(X)) <= e_row(Y.shape[1] + X.shape[1])
     if Y.shape[1]:
         assert np.linalg.norm(B - Bo) <= E_B * np.linalg.norm(X), np.linalg.norm(B - Bo) / np.linalg.norm(X)
     return Bo, Ro
