@@ -171,7 +171,8 @@ def main() -> int:
     q.load()
     m, n = args.m, args.n
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
-    tuned = {}
+    tuned = {}       # the launch parameters in effect per n (defaults resolved)
+    tuned_raw = {}   # what was passed to qless_tune_set (0 = library default)
     tune_src = None
     if args.autotune:
         from paper_2603_20889_amd import autotune
@@ -188,13 +189,15 @@ def main() -> int:
     if tune_src:
         data = json.load(open(tune_src))
         for k, v in data["table"].items():
-            q.qless_tune_set(int(k), int(v["waves_per_cu"]), int(v["fan_in"]), int(v["rows_per_lane"]))
+            tuned_raw[int(k)] = (int(v["waves_per_cu"]), int(v["fan_in"]), int(v["rows_per_lane"]))
+            q.qless_tune_set(int(k), *tuned_raw[int(k)])
             tuned[int(k)] = q.qless_tune_get(int(k))
         log("tuning table %s applied (taken on kernel sources %s, now %s)" %
             (tune_src, data.get("kernel_hash"), kernel_source_hash()))
     for item in filter(None, args.tune.split(",")):
         f = [int(v) for v in item.split(":")] + [0, 0]
-        q.qless_tune_set(f[0], f[2], f[3], f[1])
+        tuned_raw[f[0]] = (f[2], f[3], f[1])
+        q.qless_tune_set(f[0], *tuned_raw[f[0]])
         tuned[f[0]] = q.qless_tune_get(f[0])
     if tuned:
         log("tuning overrides: %s" % tuned)
@@ -351,7 +354,7 @@ def main() -> int:
     if not args.no_sweep:
         out["sweep"] = bench_sweep(q, wl, dev, log, [int(v) for v in args.ns.split(",") if v],
                                    ks=tuple(int(v) for v in args.sweep_ks.split(",") if v),
-                                   cpu_threads=cpu_threads, tuned=tuned)
+                                   cpu_threads=cpu_threads, tuned=tuned, tuned_raw=tuned_raw)
 
     if not args.no_batched:
         out["batched"] = bench_batched(q, wl, dev, log)
@@ -368,7 +371,8 @@ CPU_SWEEP_MAX_N_ALL = 32
 CPU_SWEEP_MAX_N_ONE = 8
 
 
-def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads=None, tuned=None):
+def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads=None, tuned=None,
+                tuned_raw=None):
     """Column sweep m = 2^25, n in ns, sigma log-spaced to 10^-k, k in ks
     (default {0, 4, 8}): accuracy of TSQR and CholQR2 for every (n, k); timing
     (k = 4) of the TSQR launch (HIP events around it) and of the whole
@@ -434,7 +438,7 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads
                     q.timing_enable(False)
                     dk_ms, dk_cnt = q.timing_read("tsqr_stage1")
                     q.timing_reset()
-                    q.qless_tune_set(ns, tuned_n["waves_per_cu"], tuned_n["fan_in"], tuned_n["rows_per_lane"])
+                    q.qless_tune_set(ns, *tuned_raw[ns])
                     rec["tsqr_ms_default"] = round(dk_ms / max(dk_cnt, 1), 5)
                     if flush is None:
                         rec["tsqr_step_ms_default"] = round(d_ms, 5)

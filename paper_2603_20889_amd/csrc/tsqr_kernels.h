@@ -955,9 +955,13 @@ __device__ __forceinline__ void fold_rows_g16(const double* __restrict__ X, int 
 // with one row per lane; v_mfma_f64_16x16x4f64).  A panel of 64 rows W is
 // held in registers as NB = NP/16 column blocks in the matrix-core operand
 // layout: register c of lane l of block K holds W[4c + l/16][16K + l%16].
-// Block J is folded into the running R column by column -- the reflectors
-// of the unblocked fold, with their pivot entries u0_j and gamma_j recorded
-// -- after a transpose through LDS to one row per lane.  Its 16 reflectors
+// That is also the 4 x 16 column-group layout with 16 rows per lane (row
+// group l/16, column l%16 of the block), so block J is folded into the
+// running R column by column in place -- the reflectors of the unblocked
+// fold (pivot column broadcast by DPP row_newbcast, sums over the 4 row
+// groups), with their pivot entries u0_j and gamma_j recorded -- and what
+// the fold leaves in its registers is V, the reflectors' part in W, already
+// in the operand layout of V^T V and V^T W_K.  Its 16 reflectors
 // H_j = I - gamma_j u_j u_j^T then act on the later blocks at once in
 // compact WY form (forward, columnwise: H_0 H_1 ... H_15 = I - U T U^T with
 // T_jj = gamma_j and T_{0:j,j} = -gamma_j T_{0:j,0:j} U_{:,0:j}^T u_j).  U
@@ -969,9 +973,9 @@ __device__ __forceinline__ void fold_rows_g16(const double* __restrict__ X, int 
 //   R_{J,K} -= diag(u0) S',  W_K -= V S'        (16)
 // which is applying the 16 reflectors in turn with the sums regrouped.
 //
-// Per-wavefront LDS scratch (doubles): the 64 x 16 transpose buffer (row
-// stride 17), V^T V (16 x 16), T (stride 17), the recorded u0 and gamma,
-// and the coefficient exchange of the column fold.
+// V S' takes V with rows on the lane's low bits, so V goes through LDS once
+// per block.  Per-wavefront LDS scratch (doubles): that 64 x 16 buffer (row
+// stride 17), V^T V (16 x 16), T (stride 17), the recorded u0 and gamma.
 typedef double mf64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfVs = 17;                       // row stride of the transpose buffer and of T
@@ -979,8 +983,7 @@ constexpr int kMfV = 0;                         // 64 x 16 (stride 17)
 constexpr int kMfY = kMfV + 64 * kMfVs;         // 16 x 16
 constexpr int kMfT = kMfY + 256;                // 16 x 16 (stride 17)
 constexpr int kMfRec = kMfT + 16 * kMfVs;       // u0[16], gamma[16]
-constexpr int kMfCw = kMfRec + 32;              // 16
-constexpr int kMfScratch = kMfCw + 16;
+constexpr int kMfScratch = kMfRec + 32;
 
 // Block KB (columns 16KB..16KB+15) of the 64-row panel at row `base`, in
 // the operand layout; rows >= r_end and columns >= n read as zero.
@@ -1014,38 +1017,71 @@ __device__ __forceinline__ void mf_load_panel(double (&g)[NP / 16][16], const do
     }
 }
 
+// Step j of the fold of diagonal block JB (column J = 16 JB + j) in the 4 x
+// 16 layout, 16 rows per lane: x[c] is row 4c + l/16 of the panel, column
+// 16 JB + l%16.  Only the block's own columns are updated (R row J, columns
+// 16 JB .. 16 JB + 15, and x); u0_j and gamma_j go to rec[j], rec[16 + j]
+// (0 and 0 for a column left as it is).
+template <int NP, int JB, int j>
+struct FoldStepBlk {
+    __device__ static __forceinline__ void run(double (&x)[16], double* __restrict__ Rw, double* __restrict__ rec,
+                                               int lane) {
+        if constexpr (j < 16) {
+            constexpr int J = 16 * JB + j;
+            const int cg = lane % kG4;
+            const bool live = cg > j;
+            double piv[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) piv[c] = bcast_row16<j>(x[c]);
+            const double r = Rw[tri_row<NP>(J) + (live ? cg - j : 0)];
+            double p = 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) p = fma(piv[c], x[c], p);
+            p = sum_over_row_groups4(p);
+            const double s = readlane_f64(p, j);       // |panel part of column J|^2
+            const double alpha = readlane_f64(r, j);   // R_JJ
+            if (reflector_needed(alpha, s)) {
+                double beta, u0, gamma;
+                reflector_scalars(alpha, s, beta, u0, gamma);
+                const double coef = live ? gamma * fma(u0, r, p) : 0.0;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) x[c] = live ? fma(-coef, piv[c], x[c]) : x[c];
+                if (lane < kG4) Rw[live ? tri_row<NP>(J) + cg - j : tri_size<NP>() + cg] = fma(-coef, u0, r);
+                if (lane == 0) {
+                    Rw[tri_row<NP>(J)] = beta;
+                    rec[j] = u0;
+                    rec[16 + j] = gamma;
+                }
+            } else if (lane == 0) {
+                rec[j] = 0.0;
+                rec[16 + j] = 0.0;
+            }
+            FoldStepBlk<NP, JB, j + 1>::run(x, Rw, rec, lane);
+        }
+    }
+};
+
 // Block JB of the panel in g: fold it into R (Rw, packed NP x NP), apply its
-// reflectors to blocks JB+1.., and start loading block JB of the next panel
-// (row `next`) into the registers it frees.
+// reflectors to blocks JB+1.., and load block JB of the next panel (row
+// `next`) into the registers it frees.
 template <int NP, int JB>
 __device__ __forceinline__ void mf_fold_block(double (&g)[NP / 16][16], double* __restrict__ Rw,
-                                              double* __restrict__ scr, const LaneOrigins<16>& org, int lane,
-                                              const double* __restrict__ X, int n, int64_t ldx, int64_t next,
-                                              int64_t r_end, bool fast) {
+                                              double* __restrict__ scr, int lane, const double* __restrict__ X,
+                                              int n, int64_t ldx, int64_t next, int64_t r_end, bool fast) {
     constexpr int NB = NP / 16;
     const int lo = lane & 15, hi = lane >> 4;
-    double* __restrict__ Vt = scr + kMfV;
     double* __restrict__ rec = scr + kMfRec;
-    // block JB to one row per lane
-#pragma unroll
-    for (int c = 0; c < 16; ++c) Vt[(4 * c + hi) * kMfVs + lo] = g[JB][c];
-    double x[1][16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) x[0][t] = Vt[lane * kMfVs + t];
-    if (next < r_end) mf_load_block<JB>(g[JB], X, n, ldx, next, r_end, fast, lane);
-    // column fold of the diagonal block (rows 16JB.. of R), reflectors recorded
-    FoldStep<16, 1, 0, true, NP - 16 * JB>::run(x, Rw + tri_row<NP>(16 * JB), scr + kMfCw, org, lane, rec);
+    // the x of the column fold keeps its dead columns unchanged, so what is
+    // left in g[JB] is V: column j holds the panel part of reflector j
+    FoldStepBlk<NP, JB, 0>::run(g[JB], Rw, rec, lane);
     if constexpr (JB + 1 < NB) {
-        // x[0][t] = V[lane][t]: the reflector parts in W
+        double* __restrict__ Vt = scr + kMfV;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) Vt[lane * kMfVs + t] = x[0][t];
-        double vg[16];                       // V in the operand layout
-#pragma unroll
-        for (int c = 0; c < 16; ++c) vg[c] = Vt[(4 * c + hi) * kMfVs + lo];
+        for (int c = 0; c < 16; ++c) Vt[(4 * c + hi) * kMfVs + lo] = g[JB][c];
         // Y = V^T V
         mf64x4 y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < 16; ++c) y = __builtin_amdgcn_mfma_f64_16x16x4f64(vg[c], vg[c], y, 0, 0, 0);
+        for (int c = 0; c < 16; ++c) y = __builtin_amdgcn_mfma_f64_16x16x4f64(g[JB][c], g[JB][c], y, 0, 0, 0);
         double* __restrict__ Y = scr + kMfY;
 #pragma unroll
         for (int v = 0; v < 4; ++v) Y[(4 * v + hi) * 16 + lo] = y[v];
@@ -1091,7 +1127,7 @@ __device__ __forceinline__ void mf_fold_block(double (&g)[NP / 16][16], double* 
                 s[v] = u0r[v] * Rw[ri[v]];
             }
 #pragma unroll
-            for (int c = 0; c < 16; ++c) s = __builtin_amdgcn_mfma_f64_16x16x4f64(vg[c], g[K][c], s, 0, 0, 0);
+            for (int c = 0; c < 16; ++c) s = __builtin_amdgcn_mfma_f64_16x16x4f64(g[JB][c], g[K][c], s, 0, 0, 0);
             mf64x4 sp = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < 4; ++c) sp = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[c], s[c], sp, 0, 0, 0);
@@ -1106,8 +1142,9 @@ __device__ __forceinline__ void mf_fold_block(double (&g)[NP / 16][16], double* 
                 for (int v = 0; v < 4; ++v) g[K][4 * u + v] = acc[v];
             }
         }
-        mf_fold_block<NP, JB + 1>(g, Rw, scr, org, lane, X, n, ldx, next, r_end, fast);
     }
+    if (next < r_end) mf_load_block<JB>(g[JB], X, n, ldx, next, r_end, fast, lane);
+    if constexpr (JB + 1 < NB) mf_fold_block<NP, JB + 1>(g, Rw, scr, lane, X, n, ldx, next, r_end, fast);
 }
 
 // Fold rows [r_begin, r_end) of X (n <= NP columns) into Rw, 64 rows at a
@@ -1118,13 +1155,11 @@ __device__ __forceinline__ void fold_rows_mfma(const double* __restrict__ X, int
                                                int lane) {
     static_assert(NP % 16 == 0, "the matrix-core fold works on 16-column blocks");
     if (r_begin >= r_end) return;
-    LaneOrigins<16> org;
-    org.init(lane);
     const bool fast = n == NP && (int64_t)64 * ldx * 8 < 0x7FFFFFFF;
     double g[NP / 16][16];
     mf_load_panel<NP, 0>(g, X, n, ldx, r_begin, r_end, fast, lane);
     for (int64_t base = r_begin; base < r_end; base += 64)
-        mf_fold_block<NP, 0>(g, Rw, scr, org, lane, X, n, ldx, base + 64, r_end, fast);
+        mf_fold_block<NP, 0>(g, Rw, scr, lane, X, n, ldx, base + 64, r_end, fast);
 }
 
 template <int NP, int RPL>
@@ -1220,13 +1255,13 @@ __device__ __forceinline__ void fold_block_triangles(double* __restrict__ Rsh0, 
     }
 }
 
-// The n = 64 matrix-core instance needs more than 256 registers per lane
-// (one wavefront per SIMD); every other instance is built for two.  (Three
+// The n = 48 and 64 matrix-core instances need more than 256 registers per
+// lane (one wavefront per SIMD); every other instance is built for two.  (Three
 // per SIMD for the n = 16 fold with three rows per lane, at most 168
 // registers, measured 3 % slower than two with four rows per lane.)
 template <int NP, int RPL>
 constexpr int fold_waves_per_eu() {
-    return (mf_instance<NP, RPL>() && NP > 48) ? 1 : 2;
+    return (mf_instance<NP, RPL>() && NP >= 48) ? 1 : 2;
 }
 
 // One launch of Alg. 2 (stage 1 or a tree level): wavefront w folds rows
