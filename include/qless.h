@@ -256,7 +256,10 @@ int qless_q_from_r(const double *X, int64_t m, int64_t n, int64_t ldx, const dou
  * p >= 0, n >= 1, p + n <= QLESS_MAX_N (else QLESS_ERR_UNSUPPORTED).
  * X: device, m x n row-major, ldx >= n.  B: device, p x n row-major,
  * ldb >= n (may be NULL when p == 0).  R: device, n x n, ldr >= n, diagonal
- * >= 0.  B and R must not overlap Y or X.  Workspace of
+ * >= 0.  B and R must not overlap Y or X.  The kernel addresses one panel of
+ * rows (at most 2048) of Y and X with 32-bit byte offsets: a leading
+ * dimension ldy or ldx for which a panel would span 2^31 bytes or more
+ * (never below 131072) gives QLESS_ERR_UNSUPPORTED.  Workspace of
  * qless_two_phase_workspace_bytes(m, p, n) bytes (0 for invalid sizes).
  */
 size_t qless_two_phase_workspace_bytes(int64_t m, int64_t p, int64_t n);

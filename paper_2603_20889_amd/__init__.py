@@ -476,6 +476,11 @@ def svqb_q(X, Q=None, Z=None, sigma=None, info=None, trunc_tol: float = 0.0, wor
     return Q, Z, sigma, info
 
 
+# Leading dimensions from which qless_two_phase_r gets compact copies (a
+# panel of the fold spans at most 2048 rows, addressed with 32-bit offsets).
+TWO_PHASE_LD_COPY = 1 << 17
+
+
 def qless_two_phase_r(Y, X, B=None, R=None, work=None):
     """Two-phase orthogonalisation in one pass (Sec. 2): B = Y^T X (p x n) and
     R = R((I - Y Y^T) X) (n x n) for Y with orthonormal columns."""
@@ -485,6 +490,12 @@ def qless_two_phase_r(Y, X, B=None, R=None, work=None):
     Y, my, p, ldy = _matrix(Y, "Y")
     if my != m or Y.device != dev:
         raise ValueError("Y must have X's rows and live on X's device")
+    # a leading dimension this large is outside what the kernel addresses
+    # (QLESS_ERR_UNSUPPORTED): pass compact copies instead
+    if ldx >= TWO_PHASE_LD_COPY:
+        X, ldx = X.contiguous(), n
+    if ldy >= TWO_PHASE_LD_COPY:
+        Y, ldy = Y.contiguous(), p
     with torch.cuda.device(dev):
         if B is None:
             B = torch.empty((p, n), dtype=torch.float64, device=dev)

@@ -1,6 +1,8 @@
 // Host side of the one-pass two-phase orthogonalisation (qless_two_phase_r):
 // plan, the stage-1 fold over [Y X], the tree of qless_tsqr_r and the split
 // of the (p+n) x (p+n) R into B = R12 and R = R22.
+#include <algorithm>
+
 #include "twophase_kernels.h"
 
 namespace qless {
@@ -92,6 +94,10 @@ int qless_two_phase_r(const double* Y, int64_t p, int64_t ldy, const double* X, 
     if (p > 0 && m > 0 && (Y == nullptr || ldy < p)) return QLESS_ERR_ARG;
     const int64_t w = p + n;
     const TsqrPlan plan = cat_plan(m, w);
+    // the kernel addresses a panel with 32-bit byte offsets
+    const int64_t ld_max = std::max(p > 0 ? ldy : 0, m > 0 ? ldx : n);
+    if (m > 0 && tsqr_panel_rows(plan.npad, plan.rows_per_lane) * ld_max * 8 >= 0x7FFFFFFF)
+        return QLESS_ERR_UNSUPPORTED;
     const size_t need = two_phase_work(plan, w);
     if (work == nullptr || (reinterpret_cast<uintptr_t>(work) & 255u) != 0 || work_bytes < need)
         return QLESS_ERR_WORKSPACE;

@@ -28,51 +28,190 @@ struct CatSrc {
     int n;
 };
 
-// Source of column c of [Y X]: its base pointer and row stride (null for a
-// padding column c >= p + n).  Chosen once per column, not per element.
-__device__ __forceinline__ const double* cat_col(const CatSrc& s, int c, int64_t& ld) {
-    if (c < s.p) {
-        ld = s.ldy;
-        return s.Y + c;
-    }
-    ld = s.ldx;
-    return c < s.p + s.n ? s.X + (c - s.p) : nullptr;
+// Full panels (all 64 RPL or 8 RPL rows present) through buffer loads, as
+// the TSQR fold loads X: one resource per source, rebased at the panel, the
+// row offset of a lane in a VGPR and the stripe offset in an SGPR.  Whether
+// a column comes from Y or X is the same for every lane in the n <= 16
+// layout; in the column-group layout it is the same for every lane of a
+// column slot except the one slot that straddles column p, which takes both
+// loads under complementary lane masks.  Columns >= p + n are zero.  The
+// host rejects leading dimensions for which a panel's byte offsets would not
+// fit 31 bits.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cat_rsrc(const double* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, 0x7FFFFFFF, 0x00020000);
 }
 
-// Layout of n <= 16 (lane l holds rows base + l + 64 i, every column).
+__device__ __forceinline__ double cat_ld(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+
+__device__ __forceinline__ f64x2 cat_ld2(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
+
+// Element c of a row: wave-uniform branches on the source.
+__device__ __forceinline__ double cat_elem(const CatSrc& s, __amdgpu_buffer_rsrc_t ry, __amdgpu_buffer_rsrc_t rx,
+                                           int vy, int vx, int sy, int sx, int c) {
+    if (c < s.p) return cat_ld(ry, vy + c * 8, sy);
+    if (c < s.p + s.n) return cat_ld(rx, vx + (c - s.p) * 8, sx);
+    return 0.0;
+}
+
 template <int NP, int RPL>
-__device__ __forceinline__ void load_cat_1d(double (&x)[RPL][NP], const CatSrc& s, int64_t base, int64_t r_end,
-                                            int lane) {
-    const double* col[NP];
-    int64_t ld[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) col[c] = cat_col(s, c, ld[c]);   // wave-uniform
-    // a row's columns back to back, so that each cache line is fetched once
+__device__ __forceinline__ void load_cat_1d_fast(double (&x)[RPL][NP], const CatSrc& s, int64_t base, int lane) {
+    const __amdgpu_buffer_rsrc_t ry = cat_rsrc(s.p > 0 ? s.Y + base * s.ldy : s.X);
+    const __amdgpu_buffer_rsrc_t rx = cat_rsrc(s.X + base * s.ldx);
+    const int vy = lane * (int)(s.ldy * 8), vx = lane * (int)(s.ldx * 8);
+    const int sy = (int)(kWave * s.ldy * 8), sx = (int)(kWave * s.ldx * 8);
+    const int w = s.p + s.n;
+    // a row's columns back to back; two columns of one source in one 16-byte load
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-        const int64_t row = base + lane + (int64_t)kWave * i;
 #pragma unroll
-        for (int c = 0; c < NP; ++c) x[i][c] = (col[c] != nullptr && row < r_end) ? col[c][row * ld[c]] : 0.0;
+        for (int c = 0; c < NP; c += 2) {
+            if (c + 1 < NP && c + 1 < s.p) {
+                const f64x2 v = cat_ld2(ry, vy + c * 8, sy * i);
+                x[i][c] = v[0];
+                x[i][c + 1] = v[1];
+            } else if (c + 1 < NP && c >= s.p && c + 1 < w) {
+                const f64x2 v = cat_ld2(rx, vx + (c - s.p) * 8, sx * i);
+                x[i][c] = v[0];
+                x[i][c + 1] = v[1];
+            } else {
+                x[i][c] = cat_elem(s, ry, rx, vy, vx, sy * i, sx * i, c);
+                if (c + 1 < NP) x[i][c + 1] = cat_elem(s, ry, rx, vy, vx, sy * i, sx * i, c + 1);
+            }
+        }
     }
 }
 
-// Layout of 16 < n <= 64 (lane (rg, cg) holds rows base + rg + 8 i, columns
-// cg + 8 u).
+
 template <int NP, int RPL>
-__device__ __forceinline__ void load_cat_2d(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
-                                            int64_t r_end, int lane) {
+__device__ __forceinline__ void load_cat_2d_fast(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
+                                                 int lane) {
     constexpr int NC = NP / kG2;
     const int rg = lane / kG2, cg = lane % kG2;
-    const double* col[NC];
-    int64_t ld[NC];
+    const __amdgpu_buffer_rsrc_t ry = cat_rsrc(s.p > 0 ? s.Y + base * s.ldy : s.X);
+    const __amdgpu_buffer_rsrc_t rx = cat_rsrc(s.X + base * s.ldx);
+    const int sy = (int)(kRG2 * s.ldy * 8), sx = (int)(kRG2 * s.ldx * 8);
+    const int w = s.p + s.n;
 #pragma unroll
-    for (int u = 0; u < NC; ++u) col[u] = cat_col(s, cg + kG2 * u, ld[u]);
+    for (int u = 0; u < NC; ++u) {
+        const int c = cg + kG2 * u;
+        const int c0 = kG2 * u;                        // first column of the slot (wave-uniform)
+        if (c0 + kG2 <= s.p) {                         // every lane reads Y
+            const int vo = (int)((rg * s.ldy + c) * 8);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) x[i][u] = cat_ld(ry, vo, sy * i);
+        } else if (c0 >= s.p) {                        // every lane reads X (or padding)
+            const bool ok = c < w;
+            const int vo = (int)((rg * s.ldx + (ok ? c - s.p : 0)) * 8);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const double v = cat_ld(rx, vo, sx * i);
+                x[i][u] = ok ? v : 0.0;
+            }
+        } else {                                       // the slot across column p
+            const bool fy = c < s.p, ok = c < w;
+            const int vo = fy ? (int)((rg * s.ldy + c) * 8) : (int)((rg * s.ldx + (ok ? c - s.p : 0)) * 8);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                double v;
+                if (fy) v = cat_ld(ry, vo, sy * i);
+                else v = cat_ld(rx, vo, sx * i);
+                x[i][u] = (fy || ok) ? v : 0.0;
+            }
+        }
+    }
+}
+
+
+// The last, partial panel of a wavefront (rows_left < the panel's rows): a
+// row past the end reads the panel's first row (in bounds) and is zeroed.
+template <int NP, int RPL>
+__device__ __forceinline__ void load_cat_1d_part(double (&x)[RPL][NP], const CatSrc& s, int64_t base,
+                                                 int rows_left, int lane) {
+    const __amdgpu_buffer_rsrc_t ry = cat_rsrc(s.p > 0 ? s.Y + base * s.ldy : s.X);
+    const __amdgpu_buffer_rsrc_t rx = cat_rsrc(s.X + base * s.ldx);
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-        const int64_t row = base + rg + (int64_t)kRG2 * i;
+        const int row = lane + kWave * i;
+        const bool ok = row < rows_left;
+        const int vy = (ok ? row : 0) * (int)(s.ldy * 8), vx = (ok ? row : 0) * (int)(s.ldx * 8);
 #pragma unroll
-        for (int u = 0; u < NC; ++u) x[i][u] = (col[u] != nullptr && row < r_end) ? col[u][row * ld[u]] : 0.0;
+        for (int c = 0; c < NP; ++c) {
+            double v = 0.0;
+            if (c < s.p) v = cat_ld(ry, vy + c * 8, 0);
+            else if (c < s.p + s.n) v = cat_ld(rx, vx + (c - s.p) * 8, 0);
+            x[i][c] = ok ? v : 0.0;
+        }
     }
+}
+
+template <int NP, int RPL>
+__device__ __forceinline__ void load_cat_2d_part(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
+                                                 int rows_left, int lane) {
+    constexpr int NC = NP / kG2;
+    const int rg = lane / kG2, cg = lane % kG2;
+    const __amdgpu_buffer_rsrc_t ry = cat_rsrc(s.p > 0 ? s.Y + base * s.ldy : s.X);
+    const __amdgpu_buffer_rsrc_t rx = cat_rsrc(s.X + base * s.ldx);
+    const int w = s.p + s.n;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int row = rg + kRG2 * i;
+        const bool ok = row < rows_left;
+        const int r = ok ? row : 0;
+#pragma unroll
+        for (int u = 0; u < NC; ++u) {
+            const int c = cg + kG2 * u;
+            double v;
+            if (c < s.p) v = cat_ld(ry, (int)((r * s.ldy + c) * 8), 0);
+            else v = cat_ld(rx, (int)((r * s.ldx + (c < w ? c - s.p : 0)) * 8), 0);
+            x[i][u] = (ok && c < w) ? v : 0.0;
+        }
+    }
+}
+
+// Lane-private fold (n <= 8) of the full panels [base, base + nfull*PANEL)
+// read by the two-source loader: the structure of the TSQR fold's
+// lane-private path (each lane folds its own rows into its own triangle in
+// registers, panel p+1 loaded while panel p is folded, the 64 triangles
+// combined once at the end by the cross-lane fold).
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_cat_lane_private(const CatSrc& s, int64_t base, int64_t nfull,
+                                                      double* __restrict__ Rw, double* __restrict__ Cw,
+                                                      const LaneOrigins<NP>& org, int lane) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    double Rl[tri_size<NP>()];
+#pragma unroll
+    for (int e = 0; e < tri_size<NP>(); ++e) Rl[e] = 0.0;
+    double xa[RPL][NP];
+    if constexpr (double_buffered<NP, RPL>()) {
+        double xb[RPL][NP];
+        const int64_t last = base + (nfull - 1) * PANEL;
+        load_cat_1d_fast<NP, RPL>(xa, s, base, lane);
+        while (true) {
+            load_cat_1d_fast<NP, RPL>(xb, s, base + PANEL < last ? base + PANEL : last, lane);
+            LaneFoldStep<NP, RPL, 0>::run(xa, Rl);
+            base += PANEL;
+            if (base > last) break;
+            load_cat_1d_fast<NP, RPL>(xa, s, base + PANEL < last ? base + PANEL : last, lane);
+            LaneFoldStep<NP, RPL, 0>::run(xb, Rl);
+            base += PANEL;
+            if (base > last) break;
+        }
+    } else {
+        for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+            load_cat_1d_fast<NP, RPL>(xa, s, base, lane);
+            LaneFoldStep<NP, RPL, 0>::run(xa, Rl);
+        }
+    }
+    double xe[NP][NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) xe[i][c] = (c >= i) ? Rl[tri_row<NP>(i) + c - i] : 0.0;
+    FoldStep<NP, NP, 0>::run(xe, Rw, Cw, org, lane);
 }
 
 template <int NP, int RPL>
@@ -83,16 +222,36 @@ __device__ __forceinline__ void fold_rows_cat(const CatSrc& s, int64_t r_begin, 
         LaneOrigins<NP> org;
         org.init(lane);
         double* Cw = Rw + tri_size<NP>();
-        for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        int64_t base = r_begin;
+        if constexpr (lane_private<NP>()) {
+            // n <= 8: lane-private folds of the full panels, as in the TSQR fold
+            const int64_t nfull = (r_end - r_begin) / PANEL;
+            if (nfull >= kLanePrivateMin) {
+                fold_cat_lane_private<NP, RPL>(s, base, nfull, Rw, Cw, org, lane);
+                base += nfull * PANEL;
+            }
+        }
+        for (; base + PANEL <= r_end; base += PANEL) {
             double x[RPL][NP];
-            load_cat_1d<NP, RPL>(x, s, base, r_end, lane);
+            load_cat_1d_fast<NP, RPL>(x, s, base, lane);
+            FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
+        }
+        if (base < r_end) {                       // the partial last panel
+            double x[RPL][NP];
+            load_cat_1d_part<NP, RPL>(x, s, base, (int)(r_end - base), lane);
             FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
         }
     } else {
         constexpr int64_t PANEL = (int64_t)kRG2 * RPL;
-        for (int64_t base = r_begin; base < r_end; base += PANEL) {
+        int64_t base = r_begin;
+        for (; base + PANEL <= r_end; base += PANEL) {
             double x[RPL][NP / kG2];
-            load_cat_2d<NP, RPL>(x, s, base, r_end, lane);
+            load_cat_2d_fast<NP, RPL>(x, s, base, lane);
+            FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
+        }
+        if (base < r_end) {                       // the partial last panel
+            double x[RPL][NP / kG2];
+            load_cat_2d_part<NP, RPL>(x, s, base, (int)(r_end - base), lane);
             FoldStep2D<NP, RPL, 0>::run(x, Rw, lane);
         }
     }

@@ -128,6 +128,11 @@ def test_two_phase_argument_errors_on_host():
     assert need > 0 and lib.qless_two_phase_workspace_bytes(100, 40, 30) == 0
     assert lib.qless_two_phase_r(FAKE, 4, 4, FAKE, 10_000_000, 3, 3, FAKE, 3, FAKE, 3, FAKE, need - 1, NULL) == \
         q.QLESS_ERR_WORKSPACE
+    # a leading dimension whose panel would not fit 32-bit byte offsets (width 7:
+    # 256-row panels, so ld 2^20 spans 2 GiB), before any launch
+    for ldy, ldx in ((1 << 20, 3), (4, 1 << 20)):
+        assert lib.qless_two_phase_r(FAKE, 4, ldy, FAKE, 10_000_000, 3, ldx, FAKE, 3, FAKE, 3, FAKE, need,
+                                     NULL) == q.QLESS_ERR_UNSUPPORTED
 
 
 def test_q_from_r_argument_errors_on_host():

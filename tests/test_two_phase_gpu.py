@@ -103,3 +103,15 @@ def test_two_phase_argument_errors(gpu):
         q.qless_two_phase_r(Y, X)           # p + n = 70 > 64
     with pytest.raises(ValueError):
         q.qless_two_phase_r(Y[:50], X)      # row counts differ
+
+
+# Enough rows that every stage-1 wavefront folds at least four full panels,
+# so the lane-private fold of the narrow widths (p + n <= 8) runs, with its
+# partial last panel; Y orthonormal, X iid N(0, 1), checked against the oracle.
+@pytest.mark.parametrize("m,p,n", [(2_100_000, 4, 4), (4_300_000, 1, 3), (3_300_000, 2, 5)])
+def test_two_phase_lane_private(gpu, m, p, n):
+    print("case two-phase lane-private m=%d p=%d n=%d" % (m, p, n), flush=True)
+    Y = wl.orthonormal_columns(m, p, wl.rng(m + p))
+    X = wl.gaussian(m, n, seed=m + n)
+    B, R = run(Y, X, gpu)
+    check(Y, X, B, R)
