@@ -74,6 +74,9 @@ SHAPES = [
     (9999, 8), (12345, 9), (20000, 10), (3000, 12), (40001, 13), (50000, 16), (777, 17), (20000, 20),
     (33333, 24), (10000, 31), (20000, 32), (5000, 33), (8000, 40), (6000, 48), (4000, 63), (10000, 64),
     (300_001, 8), (262_144, 16),
+    # padded widths of the 4 x 16 layout (48, 64) and several panels per wavefront
+    # through the staged cross-lane fold (10, 16)
+    (7000, 45), (300_001, 45), (200_003, 61), (150_000, 10), (400_000, 16),
 ]
 
 
