@@ -50,18 +50,20 @@ int batch_np(int64_t n) {
 
 // Panel rows of the instance of a padded width (tiles are whole panels).
 int64_t batch_panel_rows(int np) {
+    using batch_detail::batch_rpl;
+    using tsqr_detail::panel_rows;
     switch (np) {
-        case 1: return 64 * 32;
-        case 2: return 64 * 16;
-        case 4: return 64 * 8;
-        case 8: return 64 * 4;
-        case 16: return 64 * 4;
-        case 24: return 8 * 21;
-        case 32: return 8 * 16;
-        case 40: return 8 * 12;
-        case 48: return 8 * 10;
-        case 56: return 8 * 8;
-        default: return 8 * 7;
+        case 1: return panel_rows<1, batch_rpl(1)>();
+        case 2: return panel_rows<2, batch_rpl(2)>();
+        case 4: return panel_rows<4, batch_rpl(4)>();
+        case 8: return panel_rows<8, batch_rpl(8)>();
+        case 16: return panel_rows<16, batch_rpl(16)>();
+        case 24: return panel_rows<24, batch_rpl(24)>();
+        case 32: return panel_rows<32, batch_rpl(32)>();
+        case 40: return panel_rows<40, batch_rpl(40)>();
+        case 48: return panel_rows<48, batch_rpl(48)>();
+        case 56: return panel_rows<56, batch_rpl(56)>();
+        default: return panel_rows<64, batch_rpl(64)>();
     }
 }
 

@@ -29,25 +29,34 @@ constexpr int kBatchClasses = 4;
 
 constexpr int batch_class(int np) { return np <= 8 ? 0 : np <= 16 ? 1 : np <= 32 ? 2 : 3; }
 
-#define QLESS_BATCH_SWITCH_0(np, CALL) \
-    switch (np) {                      \
-        case 1: CALL(1, 32); break;    \
-        case 2: CALL(2, 16); break;    \
-        case 4: CALL(4, 8); break;     \
-        default: CALL(8, 4); break;    \
+// Rows per lane of the batched instance of each padded width; the host plan
+// cuts tiles into whole panels of these instances.  The single-matrix
+// defaults, except the 8 x 8 column-group fold for 48 and 64: in one kernel
+// with 40 and 56 the 4 x 16 fold would spill.
+constexpr int batch_rpl(int np) {
+    return np == 1 ? 32 : np == 2 ? 16 : np == 4 ? 8 : np == 8 ? 4 : np == 16 ? 4 : np == 24 ? 21 : np == 32 ? 16
+         : np == 40 ? 12 : np == 48 ? 10 : np == 56 ? 8 : 7;
+}
+
+#define QLESS_BATCH_SWITCH_0(np, CALL)             \
+    switch (np) {                                  \
+        case 1: CALL(1, batch_rpl(1)); break;      \
+        case 2: CALL(2, batch_rpl(2)); break;      \
+        case 4: CALL(4, batch_rpl(4)); break;      \
+        default: CALL(8, batch_rpl(8)); break;     \
     }
-#define QLESS_BATCH_SWITCH_1(np, CALL) { CALL(16, 4); }
-#define QLESS_BATCH_SWITCH_2(np, CALL) \
-    switch (np) {                      \
-        case 24: CALL(24, 21); break;  \
-        default: CALL(32, 16); break;  \
+#define QLESS_BATCH_SWITCH_1(np, CALL) { CALL(16, batch_rpl(16)); }
+#define QLESS_BATCH_SWITCH_2(np, CALL)             \
+    switch (np) {                                  \
+        case 24: CALL(24, batch_rpl(24)); break;   \
+        default: CALL(32, batch_rpl(32)); break;   \
     }
-#define QLESS_BATCH_SWITCH_3(np, CALL) \
-    switch (np) {                      \
-        case 40: CALL(40, 12); break;  \
-        case 48: CALL(48, 10); break;  \
-        case 56: CALL(56, 8); break;   \
-        default: CALL(64, 7); break;   \
+#define QLESS_BATCH_SWITCH_3(np, CALL)             \
+    switch (np) {                                  \
+        case 40: CALL(40, batch_rpl(40)); break;   \
+        case 48: CALL(48, batch_rpl(48)); break;   \
+        case 56: CALL(56, batch_rpl(56)); break;   \
+        default: CALL(64, batch_rpl(64)); break;   \
     }
 
 // Fold tile t of matrix M (rows [t*tile_rows, ...)) and write its triangle to

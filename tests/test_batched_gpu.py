@@ -12,7 +12,8 @@ import workloads as wl
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(0, 3), (1, 4), (5, 8), (100, 1), (3000, 3), (20000, 4), (77777, 5), (4096, 8), (250_000, 8),
-          (9000, 13), (100_000, 16), (12345, 17), (60000, 32), (2000, 33), (30000, 64), (1_000_003, 4)]
+          (9000, 13), (100_000, 16), (12345, 17), (60000, 32), (2000, 33), (30000, 64), (1_000_003, 4),
+          (50000, 45), (40000, 61)]
 
 
 def make(shapes, seed0=0):
