@@ -181,6 +181,32 @@ def test_config3_full_size_known_r(gpu, n):
     assert oracle.rel_err_r(R, R0) <= E_R
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [32, 48])
+def test_config3_full_size_tuned_known_r(gpu, n):
+    """m = 2^25 in the launch configuration the benchmark uses where the
+    committed tuning table differs from the defaults (16 stage-1 wavefronts
+    per CU at n = 32 and 48), known-answer R0 normwise and row by row."""
+    import json
+    import os
+    table = json.load(open(os.path.join(os.path.dirname(q.__file__), "tuning_gfx950.json")))["table"]
+    t = table[str(n)]
+    print("case config3 tuned n=%d %s" % (n, t), flush=True)
+    X, R0 = wl.config3(n, 4, device=gpu)
+    q.qless_tune_set(n, int(t["waves_per_cu"]), int(t["fan_in"]), int(t["rows_per_lane"]))
+    try:
+        R = q.qless_tsqr_r(X)
+        torch.cuda.synchronize(gpu)
+    finally:
+        q.qless_tune_set(n, 0, 0, 0)
+    R = R.cpu().numpy()
+    floor = 1e-4 * float(torch.linalg.vector_norm(X, dim=0).max())
+    del X
+    torch.cuda.empty_cache()
+    assert oracle.rel_err_r(R, R0) <= E_R
+    assert oracle.row_scaled_err(R, R0, floor) <= e_row_bar(n)
+
+
 # Every compiled (n, rows_per_lane) instance, with one wavefront per CU so that
 # each wavefront folds at least four full panels plus part of a fifth: this
 # exercises the lane-private fold, the LDS-staged panel stream, register double
