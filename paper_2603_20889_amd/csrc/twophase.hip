@@ -12,7 +12,7 @@ namespace qless {
 // wavefront, workgroup size and tree match what the kernel writes.
 #define QLESS_CAT_INSTANCES(X)                                                                   \
     X(1, 32) X(2, 16) X(3, 12) X(4, 8) X(5, 6) X(6, 6) X(7, 4) X(8, 4) X(10, 6) X(12, 5) X(14, 4) \
-    X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 10) X(56, 8) X(64, 7)
+    X(16, 4) X(24, 21) X(32, 16) X(40, 12) X(48, 16) X(56, 8) X(64, 12)
 #define QLESS_CAT_DECL(NP, RPL)                                                                         \
     hipError_t launch_cat_np##NP##_r##RPL(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, \
                                           double* out, int64_t ldo, int64_t ostride, int normalise, hipStream_t st);

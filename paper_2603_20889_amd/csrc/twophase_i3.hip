@@ -7,16 +7,16 @@ hipError_t launch_cat_np40_r12(const tsqr_detail::CatSrc& s, int64_t m, int64_t 
                           int64_t ldo, int64_t ostride, int normalise, hipStream_t st) {
     return tsqr_detail::launch_cat_fold<40, 12>(s, m, rpw, nw, out, ldo, ostride, normalise, st);
 }
-hipError_t launch_cat_np48_r10(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out,
+hipError_t launch_cat_np48_r16(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out,
                           int64_t ldo, int64_t ostride, int normalise, hipStream_t st) {
-    return tsqr_detail::launch_cat_fold<48, 10>(s, m, rpw, nw, out, ldo, ostride, normalise, st);
+    return tsqr_detail::launch_cat_fold<48, 16>(s, m, rpw, nw, out, ldo, ostride, normalise, st);
 }
 hipError_t launch_cat_np56_r8(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out,
                           int64_t ldo, int64_t ostride, int normalise, hipStream_t st) {
     return tsqr_detail::launch_cat_fold<56, 8>(s, m, rpw, nw, out, ldo, ostride, normalise, st);
 }
-hipError_t launch_cat_np64_r7(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out,
+hipError_t launch_cat_np64_r12(const tsqr_detail::CatSrc& s, int64_t m, int64_t rpw, int64_t nw, double* out,
                           int64_t ldo, int64_t ostride, int normalise, hipStream_t st) {
-    return tsqr_detail::launch_cat_fold<64, 7>(s, m, rpw, nw, out, ldo, ostride, normalise, st);
+    return tsqr_detail::launch_cat_fold<64, 12>(s, m, rpw, nw, out, ldo, ostride, normalise, st);
 }
 }  // namespace qless

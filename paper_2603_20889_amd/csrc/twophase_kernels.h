@@ -34,7 +34,8 @@ struct CatSrc {
 // a column comes from Y or X is the same for every lane in the n <= 16
 // layout; in the column-group layout it is the same for every lane of a
 // column slot except the one slot that straddles column p, which takes both
-// loads under complementary lane masks.  Columns >= p + n are zero.  The
+// loads under complementary lane masks (G lanes per row group: 8 for the
+// 8 x 8 layout, 16 for the 4 x 16 one).  Columns >= p + n are zero.  The
 // host rejects leading dimensions for which a panel's byte offsets would not
 // fit 31 bits.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t cat_rsrc(const double* base) {
@@ -85,21 +86,20 @@ __device__ __forceinline__ void load_cat_1d_fast(double (&x)[RPL][NP], const Cat
     }
 }
 
-
-template <int NP, int RPL>
-__device__ __forceinline__ void load_cat_2d_fast(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
+template <int NP, int RPL, int G = kG2>
+__device__ __forceinline__ void load_cat_2d_fast(double (&x)[RPL][NP / G], const CatSrc& s, int64_t base,
                                                  int lane) {
-    constexpr int NC = NP / kG2;
-    const int rg = lane / kG2, cg = lane % kG2;
+    constexpr int NC = NP / G;
+    const int rg = lane / G, cg = lane % G;
     const __amdgpu_buffer_rsrc_t ry = cat_rsrc(s.p > 0 ? s.Y + base * s.ldy : s.X);
     const __amdgpu_buffer_rsrc_t rx = cat_rsrc(s.X + base * s.ldx);
-    const int sy = (int)(kRG2 * s.ldy * 8), sx = (int)(kRG2 * s.ldx * 8);
+    const int sy = (int)((kWave / G) * s.ldy * 8), sx = (int)((kWave / G) * s.ldx * 8);
     const int w = s.p + s.n;
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
-        const int c = cg + kG2 * u;
-        const int c0 = kG2 * u;                        // first column of the slot (wave-uniform)
-        if (c0 + kG2 <= s.p) {                         // every lane reads Y
+        const int c = cg + G * u;
+        const int c0 = G * u;                          // first column of the slot (wave-uniform)
+        if (c0 + G <= s.p) {                           // every lane reads Y
             const int vo = (int)((rg * s.ldy + c) * 8);
 #pragma unroll
             for (int i = 0; i < RPL; ++i) x[i][u] = cat_ld(ry, vo, sy * i);
@@ -148,22 +148,22 @@ __device__ __forceinline__ void load_cat_1d_part(double (&x)[RPL][NP], const Cat
     }
 }
 
-template <int NP, int RPL>
-__device__ __forceinline__ void load_cat_2d_part(double (&x)[RPL][NP / kG2], const CatSrc& s, int64_t base,
+template <int NP, int RPL, int G = kG2>
+__device__ __forceinline__ void load_cat_2d_part(double (&x)[RPL][NP / G], const CatSrc& s, int64_t base,
                                                  int rows_left, int lane) {
-    constexpr int NC = NP / kG2;
-    const int rg = lane / kG2, cg = lane % kG2;
+    constexpr int NC = NP / G;
+    const int rg = lane / G, cg = lane % G;
     const __amdgpu_buffer_rsrc_t ry = cat_rsrc(s.p > 0 ? s.Y + base * s.ldy : s.X);
     const __amdgpu_buffer_rsrc_t rx = cat_rsrc(s.X + base * s.ldx);
     const int w = s.p + s.n;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-        const int row = rg + kRG2 * i;
+        const int row = rg + (kWave / G) * i;
         const bool ok = row < rows_left;
         const int r = ok ? row : 0;
 #pragma unroll
         for (int u = 0; u < NC; ++u) {
-            const int c = cg + kG2 * u;
+            const int c = cg + G * u;
             double v;
             if (c < s.p) v = cat_ld(ry, (int)((r * s.ldy + c) * 8), 0);
             else v = cat_ld(rx, (int)((r * s.ldx + (c < w ? c - s.p : 0)) * 8), 0);
@@ -240,6 +240,20 @@ __device__ __forceinline__ void fold_rows_cat(const CatSrc& s, int64_t r_begin, 
             double x[RPL][NP];
             load_cat_1d_part<NP, RPL>(x, s, base, (int)(r_end - base), lane);
             FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
+        }
+    } else if constexpr (g16_instance<NP, RPL>()) {
+        // the 4 x 16 column-group layout (n = 48, 64), as in the TSQR fold
+        constexpr int64_t PANEL = (int64_t)kRG4 * RPL;
+        int64_t base = r_begin;
+        for (; base + PANEL <= r_end; base += PANEL) {
+            double x[RPL][NP / kG4];
+            load_cat_2d_fast<NP, RPL, kG4>(x, s, base, lane);
+            FoldStepG16<NP, RPL, 0>::run(x, Rw, lane);
+        }
+        if (base < r_end) {                       // the partial last panel
+            double x[RPL][NP / kG4];
+            load_cat_2d_part<NP, RPL, kG4>(x, s, base, (int)(r_end - base), lane);
+            FoldStepG16<NP, RPL, 0>::run(x, Rw, lane);
         }
     } else {
         constexpr int64_t PANEL = (int64_t)kRG2 * RPL;

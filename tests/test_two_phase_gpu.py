@@ -46,7 +46,7 @@ def check(Y, X, B, R):
 # (cross-lane fold for p + n <= 16, column groups above), ragged row counts
 CASES = [(3000, 1, 1, 0), (20000, 3, 4, 2), (50000, 4, 4, 4), (777, 2, 6, 1), (40000, 8, 8, 4), (65537, 5, 11, 3),
          (30000, 16, 8, 3), (20000, 8, 24, 4), (12345, 32, 16, 3), (9000, 16, 47, 2), (10000, 48, 16, 4),
-         (70000, 1, 63, 2), (5000, 63, 1, 0)]
+         (70000, 1, 63, 2), (5000, 63, 1, 0), (20000, 20, 28, 3), (300_001, 10, 35, 2)]
 
 
 @pytest.mark.parametrize("m,p,n,k", CASES)
