@@ -490,7 +490,9 @@ def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
     torch.cuda.synchronize()
     total_bytes = sum(8 * m * n for m, n in shapes)
     log("batched: %d independent matrices, %.1f GB" % (count, total_bytes / 1e9))
-    plan = q.BatchPlan(Xs)
+    from paper_2603_20889_amd import autotune
+    tuned = autotune.tune_batched(Xs, dev, log=log)
+    plan = q.BatchPlan(Xs, tile_bytes=tuned["tile_bytes"], waves_per_cu=tuned["waves_per_cu"])
     plan.run()
     torch.cuda.synchronize()
     t_eager, _ = time_calls(plan.run, 5, 1)
@@ -517,6 +519,7 @@ def bench_batched(q, wl, dev, log, count: int = 512, seed: int = 4):
         by_width[n] = by_width.get(n, 0) + 8 * m * n
     res = {"matrices": count, "independent_allocations": True, "total_GB": round(total_bytes / 1e9, 2),
            "GB_by_n": {str(k): round(v / 1e9, 2) for k, v in sorted(by_width.items())}, "tiles": plan.tiles,
+           "tuned_plan": tuned,
            "batched_ms": round(t_eager, 3), "batched_graph_ms": round(t_graph, 3),
            "single_launches_ms": round(t_single, 3),
            "solves_per_s": round(count / (t_graph * 1e-3), 1),

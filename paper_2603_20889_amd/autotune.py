@@ -149,11 +149,17 @@ def tune_tsqr(ns, device=None, m: int = 1 << 25, steps: int = 9, finalists: int 
 
 
 def tune_batched(Xs, device=None, tile_choices=(256 << 10, 1 << 20, 4 << 20, 16 << 20),
-                 wave_choices=(4, 8, 16), steps: int = 3, log=print) -> dict:
-    """Pick tile_bytes and waves_per_cu for a batch (list of GPU matrices)."""
+                 wave_choices=(4, 8, 16), steps: int = 3, rounds: int = 3, min_gain: float = 0.015,
+                 log=print) -> dict:
+    """Pick tile_bytes and waves_per_cu for a batch (list of GPU matrices):
+    every pair is screened (mean of `steps` calls), then the fastest and the
+    plan defaults (tile_bytes = waves_per_cu = 0) are timed again in `rounds`
+    interleaved rounds; the fastest replaces the defaults only when its median
+    is at least `min_gain` lower.  Returns {"tile_bytes", "waves_per_cu", "ms",
+    "default_ms"}."""
     import torch
-    best = None
-    for tb, wpc in itertools.product(tile_choices, wave_choices):
+
+    def time_plan(tb, wpc):
         plan = q.BatchPlan(Xs, tile_bytes=tb, waves_per_cu=wpc)
         plan.run()
         torch.cuda.synchronize(device)
@@ -163,10 +169,20 @@ def tune_batched(Xs, device=None, tile_choices=(256 << 10, 1 << 20, 4 << 20, 16 
         torch.cuda.synchronize(device)
         ms = (time.perf_counter() - t0) * 1e3 / steps
         plan.close()
-        if best is None or ms < best["ms"]:
-            best = {"tile_bytes": tb, "waves_per_cu": wpc, "ms": ms}
-    log("[autotune] batched -> %s" % json.dumps(best))
-    return best
+        return ms
+
+    screened = sorted((time_plan(tb, wpc), tb, wpc) for tb, wpc in itertools.product(tile_choices, wave_choices))
+    cand = (screened[0][1], screened[0][2])
+    times = {cand: [], (0, 0): []}
+    for _ in range(rounds):
+        for c in times:
+            times[c].append(time_plan(*c))
+    med = {c: sorted(t)[len(t) // 2] for c, t in times.items()}
+    best = cand if med[cand] < med[(0, 0)] * (1.0 - min_gain) else (0, 0)
+    out = {"tile_bytes": best[0], "waves_per_cu": best[1], "ms": med[best], "default_ms": med[(0, 0)],
+           "screened": len(screened)}
+    log("[autotune] batched -> %s" % json.dumps(out))
+    return out
 
 
 def save(table: dict, device=None, path: str | None = None) -> str:

@@ -121,3 +121,41 @@ def test_tuner_takes_a_confirmed_gain(monkeypatch):
     _fake_timer(monkeypatch, lambda c: 0.99 if c == better else 1.0)
     got = autotune.tune_tsqr([8], device="cpu", m=1024, log=lambda *a: None)[8]
     assert (got["waves_per_cu"], got["fan_in"]) == (q.qless_tune_get(8)["waves_per_cu"], 0)
+
+
+def _fake_batched(monkeypatch, cost, lucky=None):
+    """BatchPlan stand-in whose run() advances a fake clock by cost(key) per
+    call ((tile_bytes, waves_per_cu) -> seconds); `lucky` runs 20 % fast in
+    its first plan only."""
+    import torch
+    clock = [0.0]
+    plans = []
+
+    class FakePlan:
+        def __init__(self, Xs, tile_bytes=0, waves_per_cu=0):
+            self.key = (tile_bytes, waves_per_cu)
+            self.first = self.key == lucky and lucky not in plans
+            plans.append(self.key)
+
+        def run(self):
+            clock[0] += cost(self.key) * (0.8 if self.first else 1.0)
+
+        def close(self):
+            pass
+
+    monkeypatch.setattr(q, "BatchPlan", FakePlan)
+    monkeypatch.setattr(autotune.time, "perf_counter", lambda: clock[0])
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda device=None: None)
+
+
+def test_batched_tuner_keeps_defaults_against_a_lucky_screen(monkeypatch):
+    _fake_batched(monkeypatch, lambda k: 1e-3, lucky=(1 << 20, 16))
+    got = autotune.tune_batched([None], device="cpu", log=lambda *a: None)
+    assert (got["tile_bytes"], got["waves_per_cu"]) == (0, 0)
+
+
+def test_batched_tuner_takes_a_confirmed_gain(monkeypatch):
+    _fake_batched(monkeypatch, lambda k: 0.9e-3 if k == (1 << 20, 16) else 1e-3)
+    got = autotune.tune_batched([None], device="cpu", log=lambda *a: None)
+    assert (got["tile_bytes"], got["waves_per_cu"]) == (1 << 20, 16)
+    assert got["ms"] < got["default_ms"]
