@@ -263,6 +263,39 @@ def main() -> int:
     out["plain_read_reference"] = {"kernel": "torch.sum over X", "ms": round(rd_ms, 5),
                                    "GBps": round(nbytes / (rd_ms * 1e-3) / 1e9, 1)}
 
+    # the per-call distribution (outside the timed region): each call between
+    # its own pair of events, mean / median / p99
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    calls = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    out["step_ms_distribution"] = {"calls": len(calls), "mean": round(sum(calls) / len(calls), 5),
+                                   "median": round(calls[len(calls) // 2], 5),
+                                   "p99": round(calls[min(len(calls) - 1, int(0.99 * len(calls)))], 5)}
+
+    # one GPU's share of the headline at its real shape were it split over 8
+    # GPUs by rows (m / 8 x n), the cache flushed between calls
+    ms8 = m // 8
+    X8 = X[:ms8]
+    R8 = torch.empty((n, n), dtype=torch.float64, device=dev)
+    w8, _ = q._workspace(q.QLESS_METHOD_TSQR, ms8, n, dev)
+    flush8 = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for e0, e1 in evs:
+        torch.sum(flush8)
+        e0.record()
+        q.qless_tsqr_r(X8, R=R8, work=w8)
+        e1.record()
+    torch.cuda.synchronize()
+    t8 = sorted(e0.elapsed_time(e1) for e0, e1 in evs)[len(evs) // 2]
+    out["shard_of_8"] = {"m": ms8, "n": n, "ms_median": round(t8, 5),
+                         "GBps": round(tsqr_bytes(ms8, n) / (t8 * 1e-3) / 1e9, 1),
+                         "note": "rows [0, m/8) of the headline matrix: one GPU's share under an 8-way row split"}
+    del X8, R8, w8, flush8
+
     cpu_threads = None
     if not args.no_cpu:
         import oracle
