@@ -448,34 +448,45 @@ def bench_sweep(q, wl, dev, log, ns, m: int = 2 ** 25, ks=(0, 4, 8), cpu_threads
                         torch.sum(flush)       # (a read leaves no dirty lines to write back)
                     q.qless_tsqr_r(Xs, R=Rs, work=ws)
 
-                q.timing_reset()
-                q.timing_enable(True)
-                t_ms, _ = time_calls(f, steps, 2)
-                q.timing_enable(False)
-                k_ms, k_cnt = q.timing_read("tsqr_stage1")
-                q.timing_reset()
-                k_avg = k_ms / max(k_cnt, 1)
-                if tuned_n is not None:
-                    # the same calls with the library defaults, for tuned against default
-                    # (stage-1 kernel time; the whole call where no flush is interleaved)
-                    q.qless_tune_set(ns, 0, 0, 0)
-                    wd, _ = q._workspace(q.QLESS_METHOD_TSQR, m, ns, dev)
-
-                    def fd():
-                        if flush is not None:
-                            torch.sum(flush)
-                        q.qless_tsqr_r(Xs, R=Rs, work=wd)
+                def measure(fn):
+                    """(stage-1 kernel ms, whole-call ms) averaged over `steps` calls"""
                     q.timing_reset()
                     q.timing_enable(True)
-                    d_ms, _ = time_calls(fd, steps, 2)
+                    call_ms, _ = time_calls(fn, steps, 2)
                     q.timing_enable(False)
-                    dk_ms, dk_cnt = q.timing_read("tsqr_stage1")
+                    tot, cnt = q.timing_read("tsqr_stage1")
                     q.timing_reset()
+                    return tot / max(cnt, 1), call_ms
+
+                # tuned and default timed in interleaved rounds (median of 3), so
+                # that a drift of the box over time weighs on both alike
+                wd = None
+                if tuned_n is not None:
+                    q.qless_tune_set(ns, 0, 0, 0)
+                    wd, _ = q._workspace(q.QLESS_METHOD_TSQR, m, ns, dev)
                     q.qless_tune_set(ns, *tuned_raw[ns])
-                    rec["tsqr_ms_default"] = round(dk_ms / max(dk_cnt, 1), 5)
+
+                def fd():
+                    if flush is not None:
+                        torch.sum(flush)
+                    q.qless_tsqr_r(Xs, R=Rs, work=wd)
+
+                runs, druns = [], []
+                for _ in range(3):
+                    runs.append(measure(f))
+                    if tuned_n is not None:
+                        # the same calls with the library defaults, for tuned against default
+                        # (stage-1 kernel time; the whole call where no flush is interleaved)
+                        q.qless_tune_set(ns, 0, 0, 0)
+                        druns.append(measure(fd))
+                        q.qless_tune_set(ns, *tuned_raw[ns])
+                med = lambda v: sorted(v)[len(v) // 2]
+                k_avg, t_ms = med([r[0] for r in runs]), med([r[1] for r in runs])
+                if druns:
+                    rec["tsqr_ms_default"] = round(med([r[0] for r in druns]), 5)
                     if flush is None:
-                        rec["tsqr_step_ms_default"] = round(d_ms, 5)
-                    del wd
+                        rec["tsqr_step_ms_default"] = round(med([r[1] for r in druns]), 5)
+                del wd
                 gbs = tsqr_bytes(m, ns) / (k_avg * 1e-3) / 1e9
                 rec.update({"tsqr_ms": round(k_avg, 5), "tsqr_GBps": round(gbs, 1),
                             "tsqr_frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
