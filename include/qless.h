@@ -290,7 +290,9 @@ int qless_lstsq_finish(const double *Rt, int64_t n, int64_t ldr, double *x,
  * columns, rows_per_lane = 1 selects the blocked fold on the FP64 matrix
  * cores (64-row panels, 16-column blocks in compact WY form; the same
  * reflectors, sums regrouped).  Process-wide, not thread-safe;
- * query qless_workspace_bytes after changing it.  qless_tune_get returns the
+ * query qless_workspace_bytes after changing it (a call given a workspace
+ * sized under other parameters that is now too small returns
+ * QLESS_ERR_WORKSPACE before any launch).  qless_tune_get returns the
  * values in effect (defaults resolved).
  */
 int qless_tune_set(int64_t n, int32_t waves_per_cu, int32_t fan_in, int32_t rows_per_lane);
