@@ -189,3 +189,17 @@ def test_gram_entry_points_argument_errors_on_host():
     assert need > q.qless_workspace_bytes(q.QLESS_METHOD_CHOLQR2, 10_000_000, 8) // 4
     assert lib.cholqr2_dd_r(FAKE, 10_000_000, 8, 8, FAKE, 8, NULL, FAKE, need - 1, NULL) == q.QLESS_ERR_WORKSPACE
     assert lib.cholqr2_dd_r(FAKE, 100, 8, 7, FAKE, 8, NULL, FAKE, need, NULL) == q.QLESS_ERR_ARG
+
+
+def test_workspace_outdated_by_tuning_is_refused():
+    """A workspace sized under one set of launch parameters that is too small
+    for the plan under new ones is refused before any launch."""
+    lib = q.load()
+    m, n = 50_000_000, 8
+    old = lib.qless_workspace_bytes(q.QLESS_METHOD_TSQR, m, n)
+    try:
+        q.qless_tune_set(n, 16, 0, 0)      # twice the stage-1 blocks: more stacked triangles
+        assert lib.qless_workspace_bytes(q.QLESS_METHOD_TSQR, m, n) > old
+        assert lib.qless_tsqr_r(FAKE, m, n, n, FAKE, n, FAKE, old, NULL) == q.QLESS_ERR_WORKSPACE
+    finally:
+        q.qless_tune_set(n, 0, 0, 0)
