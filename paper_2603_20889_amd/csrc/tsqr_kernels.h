@@ -544,22 +544,23 @@ __device__ __forceinline__ void read_staged_panel(double (&x)[RPL][NP], const do
     }
 }
 
+// The nfull panels start at rows base, base + step, base + 2 step, ...
+// (step = one panel for a contiguous block of rows).
 template <int NP, int RPL>
 __device__ __forceinline__ void fold_panels_lane_private_staged(const double* __restrict__ X, int64_t base,
-                                                                int64_t nfull, double* __restrict__ Rw,
+                                                                int64_t nfull, int64_t step, double* __restrict__ Rw,
                                                                 double* __restrict__ Cw, const LaneOrigins<NP>& org,
                                                                 int lane, double* stage) {
-    constexpr int64_t PANEL = (int64_t)kWave * RPL;
     double Rl[tri_size<NP>()];
 #pragma unroll
     for (int e = 0; e < tri_size<NP>(); ++e) Rl[e] = 0.0;
     stage_panel<NP, RPL>(X, base, stage, lane);
-    for (int64_t p = 0; p < nfull; ++p, base += PANEL) {
+    for (int64_t p = 0; p < nfull; ++p, base += step) {
         double x[RPL][NP];
         wait_memory();                       // panel p is in LDS
         read_staged_panel<NP, RPL>(x, stage, lane);
         wait_memory();                       // and in registers: the buffer is free
-        if (p + 1 < nfull) stage_panel<NP, RPL>(X, base + PANEL, stage, lane);
+        if (p + 1 < nfull) stage_panel<NP, RPL>(X, base + step, stage, lane);
         LaneFoldStep<NP, RPL, 0>::run(x, Rl);
     }
     double xe[NP][NP];
@@ -626,7 +627,7 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
         if (nfull >= kLanePrivateMin) {
             if constexpr (staged_instance<NP, RPL>()) {
                 if (stage != nullptr && ldx == NP)
-                    fold_panels_lane_private_staged<NP, RPL>(X, base, nfull, Rw, Cw, org, lane, stage);
+                    fold_panels_lane_private_staged<NP, RPL>(X, base, nfull, PANEL, Rw, Cw, org, lane, stage);
                 else
                     fold_panels_lane_private<NP, RPL>(X, ldx, base, nfull, Rw, Cw, org, lane);
             } else {
@@ -673,6 +674,42 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
     for (; base < r_end; base += PANEL) {
         load_panel_1d_tail<NP, RPL>(xa, X, n, ldx, base, r_end, lane);
         FoldStep<NP, RPL, 0>::run(xa, Rw, Cw, org, lane);
+    }
+}
+
+// Stage 1 of the LDS-staged lane-private instances over interleaved panels.
+// With P full panels in X and W wavefronts in the launch, wavefront w folds
+// panels w, w + W, w + 2W, ... and the last wavefront also the partial panel
+// at the end, so at any moment the launch reads one window of about W
+// consecutive panels rather than W streams far apart in memory.  Measured on
+// 5e7 x 8 with the same fold, interleaved panels ran 4 % faster than one
+// contiguous block per wavefront (plain streaming reads gain about as much).
+// Only the grouping of rows into triangles changes, and any grouping is a
+// valid reduction tree (Alg. 2).  Taken when every wavefront gets at least
+// kLanePrivateMin panels; a launch decides it once, for all its wavefronts.
+template <int NP, int RPL>
+__device__ __forceinline__ bool interleaved_stage1(int64_t m, int n, int64_t ldx, int64_t nwaves) {
+    if constexpr (staged_instance<NP, RPL>())
+        return n == NP && ldx == NP && m / ((int64_t)kWave * RPL) >= kLanePrivateMin * nwaves;
+    else
+        return false;
+}
+
+template <int NP, int RPL>
+__device__ __forceinline__ void fold_rows_interleaved(const double* __restrict__ X, int64_t m, int64_t w,
+                                                      int64_t nwaves, double* __restrict__ Rw, int lane,
+                                                      double* stage) {
+    constexpr int64_t PANEL = (int64_t)kWave * RPL;
+    const int64_t P = m / PANEL;   // >= kLanePrivateMin * nwaves > w
+    LaneOrigins<NP> org;
+    org.init(lane);
+    double* Cw = Rw + tri_size<NP>();
+    fold_panels_lane_private_staged<NP, RPL>(X, w * PANEL, (P - 1 - w) / nwaves + 1, nwaves * PANEL, Rw, Cw, org,
+                                             lane, stage);
+    if (w == nwaves - 1 && P * PANEL < m) {
+        double x[RPL][NP];
+        load_panel_1d_tail<NP, RPL>(x, X, NP, NP, P * PANEL, m, lane);
+        FoldStep<NP, RPL, 0>::run(x, Rw, Cw, org, lane);
     }
 }
 
@@ -1265,8 +1302,9 @@ constexpr int fold_waves_per_eu() {
 }
 
 // One launch of Alg. 2 (stage 1 or a tree level): wavefront w folds rows
-// [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle; the
-// last wavefront of each workgroup to finish folds the triangles of
+// [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle (the
+// LDS-staged lane-private instances take interleaved panels instead, see
+// fold_rows_interleaved); the last wavefront of each workgroup to finish folds the triangles of
 // wavefronts 1.. into wavefront 0's, in that order (all kept in LDS; ordering
 // through a workgroup-scope atomic, which costs no cache maintenance), and
 // writes the workgroup's triangle at
@@ -1297,10 +1335,14 @@ tsqr_fold_kernel(const double* __restrict__ X, int64_t m, int n, int64_t ldx, in
     double* Rw = Rsh[wib];
     zero_r<NP>(Rw, lane);
     if (Yinit != nullptr && wib == 0) load_r<NP>(Rw, n, Yinit + (int64_t)blockIdx.x * ystride, ldy, lane);
-    const int64_t r_begin = w * rows_per_wave;
-    const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
-    fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane,
-                       (mf_instance<NP, RPL>() || stage_doubles<NP, RPL>() > 0) ? stage[wib] : nullptr);
+    if (interleaved_stage1<NP, RPL>(m, n, ldx, nwaves)) {
+        fold_rows_interleaved<NP, RPL>(X, m, w, nwaves, Rw, lane, stage[wib]);
+    } else {
+        const int64_t r_begin = w * rows_per_wave;
+        const int64_t r_end = (r_begin + rows_per_wave < m) ? r_begin + rows_per_wave : m;
+        fold_rows<NP, RPL>(X, n, ldx, r_begin, r_end, Rw, lane,
+                           (mf_instance<NP, RPL>() || stage_doubles<NP, RPL>() > 0) ? stage[wib] : nullptr);
+    }
     if (nvalid > 1) {
         int old = 0;
         if (lane == 0) old = __hip_atomic_fetch_add(&arrivals, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);

@@ -87,6 +87,30 @@ def test_random_shapes(gpu, m, n):
     check(X, run(X, gpu))
 
 
+# Stage 1 of n <= 8 over interleaved panels (wavefront w of W folds panels
+# w, w + W, ...): taken once every wavefront gets at least four full panels of
+# 64 * rows_per_lane rows, which at these sizes it does (about 1640 wavefronts,
+# 8192 panels or more); the ragged tail rides on the last wavefront, and the
+# multiple of a panel (4194304 x 8) has none.
+INTERLEAVED = [(16_777_216 + 2047, 1), (8_388_608 + 333, 2), (6_291_456 + 5, 3), (4_194_304 + 511, 4),
+               (3_145_728 + 100, 5), (3_145_728 + 383, 6), (2_097_152 + 1, 7), (2_600_003, 8), (4_194_304, 8)]
+
+
+@pytest.mark.parametrize("m,n", INTERLEAVED)
+def test_interleaved_stage1(gpu, m, n):
+    print("case interleaved m=%d n=%d" % (m, n), flush=True)
+    X = wl.gaussian(m, n, seed=m % 1000 + n)
+    check(X, run(X, gpu))
+
+
+def test_interleaved_stage1_deterministic(gpu):
+    X = torch.from_numpy(wl.gaussian(2_600_003, 8, seed=11)).to(gpu)
+    R1 = q.qless_tsqr_r(X)
+    R2 = q.qless_tsqr_r(X)
+    torch.cuda.synchronize(gpu)
+    assert torch.equal(R1, R2)
+
+
 def test_empty_matrix(gpu):
     R = q.qless_tsqr_r(torch.zeros((0, 5), dtype=torch.float64, device=gpu))
     torch.cuda.synchronize(gpu)
