@@ -206,11 +206,12 @@ def test_config3_full_size_known_r(gpu, n):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("n", [32, 48])
+@pytest.mark.parametrize("n", [16, 32, 48])
 def test_config3_full_size_tuned_known_r(gpu, n):
     """m = 2^25 in the launch configuration the benchmark uses where the
-    committed tuning table differs from the defaults (16 stage-1 wavefronts
-    per CU at n = 32 and 48), known-answer R0 normwise and row by row."""
+    committed tuning table differs from the defaults (4 stage-1 wavefronts
+    per CU and fan-in 32 at n = 16, 16 wavefronts per CU at n = 32 and 48),
+    known-answer R0 normwise and row by row."""
     import json
     import os
     table = json.load(open(os.path.join(os.path.dirname(q.__file__), "tuning_gfx950.json")))["table"]
