@@ -258,10 +258,13 @@ def test_every_instance(gpu, n, rpl):
 
 
 @pytest.mark.parametrize("n,chunks", [(4, [0, 50_000, 1, 300_000]), (8, [70_000, 0, 2_000_000]),
-                                      (13, [5_000, 400_000]), (16, [1_000_000, 3]), (33, [20_000, 150_000])])
+                                      (13, [5_000, 400_000]), (16, [1_000_000, 3]), (33, [20_000, 150_000]),
+                                      (8, [100_000, 2_600_003])])
 def test_running_update(gpu, n, chunks):
     """qless_tsqr_r_update over successive row chunks (empty ones included)
-    equals the R of all rows at once (Alg. 2 on the stack [R_old; X])."""
+    equals the R of all rows at once (Alg. 2 on the stack [R_old; X]).  The
+    last case's second chunk (a view 100000 rows into X) is long enough for
+    the interleaved stage 1 and ends in a partial panel."""
     m = sum(chunks)
     X = wl.gaussian(m, n, seed=77 + n)
     print("case update n=%d chunks=%s" % (n, chunks), flush=True)
