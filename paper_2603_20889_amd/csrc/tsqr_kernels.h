@@ -681,11 +681,12 @@ __device__ __forceinline__ void fold_rows_1d(const double* __restrict__ X, int n
 // With P full panels in X and W wavefronts in the launch, wavefront w folds
 // panels w, w + W, w + 2W, ... and the last wavefront also the partial panel
 // at the end, so at any moment the launch reads one window of about W
-// consecutive panels rather than W streams far apart in memory.  Measured on
-// 5e7 x 8 with the same fold, interleaved panels ran 4 % faster than one
-// contiguous block per wavefront (plain streaming reads gain about as much).
-// Only the grouping of rows into triangles changes, and any grouping is a
-// valid reduction tree (Alg. 2).  Taken when every wavefront gets at least
+// consecutive panels rather than W streams far apart in memory.  On 5e7 x 8
+// the fold loop alone ran 4 % faster over interleaved panels than over one
+// contiguous block per wavefront (plain streaming reads gain about as much),
+// and the whole stage-1 launch, combines included, 1.5-2 %.  Only the
+// grouping of rows into triangles changes, and any grouping is a valid
+// reduction tree (Alg. 2).  Taken when every wavefront gets at least
 // kLanePrivateMin panels; a launch decides it once, for all its wavefronts.
 template <int NP, int RPL>
 __device__ __forceinline__ bool interleaved_stage1(int64_t m, int n, int64_t ldx, int64_t nwaves) {
@@ -1304,8 +1305,8 @@ constexpr int fold_waves_per_eu() {
 // One launch of Alg. 2 (stage 1 or a tree level): wavefront w folds rows
 // [w*rows_per_wave, min(m, (w+1)*rows_per_wave)) of X into a triangle (the
 // LDS-staged lane-private instances take interleaved panels instead, see
-// fold_rows_interleaved); the last wavefront of each workgroup to finish folds the triangles of
-// wavefronts 1.. into wavefront 0's, in that order (all kept in LDS; ordering
+// fold_rows_interleaved); the last wavefront of each workgroup to finish
+// folds the triangles of wavefronts 1.. into wavefront 0's, in that order (all kept in LDS; ordering
 // through a workgroup-scope atomic, which costs no cache maintenance), and
 // writes the workgroup's triangle at
 // Y + blockIdx.x*ystride (leading dimension ldy).  With normalise (a single
