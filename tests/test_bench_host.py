@@ -69,6 +69,25 @@ def test_committed_traffic_record_is_consistent():
     assert d["traffic_bytes_per_launch"] >= d["algorithmic_bytes_per_launch"]
 
 
+def test_committed_profiles_name_the_current_kernel_sources():
+    """Every committed rocprofv3 summary, and the tuning table, was taken on
+    the kernel sources as they are: a change to a profiled kernel has to come
+    with new profiles."""
+    import re
+    h = bench.kernel_source_hash()
+    prof = os.path.join(ROOT, "profiles")
+    named = 0
+    for fn in sorted(os.listdir(prof)):
+        text = open(os.path.join(prof, fn)).read()
+        for found in re.findall(r"Kernel sources hash \(bench\.py `kernel_hash`[^)]*\): ([0-9a-f]{16})", text):
+            assert found == h, "%s was taken on %s, the sources are now %s" % (fn, found, h)
+            named += 1
+    assert named >= 6
+    assert json.load(open(os.path.join(prof, "tsqr_stage1_traffic.json")))["kernel_hash"] == h
+    table = json.load(open(os.path.join(ROOT, "paper_2603_20889_amd", "tuning_gfx950.json")))
+    assert table["kernel_hash"] == h
+
+
 def test_host_threads_follows_affinity_and_omp_cap(monkeypatch):
     avail = len(os.sched_getaffinity(0))
     monkeypatch.delenv("OMP_NUM_THREADS", raising=False)
